@@ -74,5 +74,6 @@ def fusion_margins(X, U, src, dst, w, gamma, q, S):
     _, s = fused_edges(X, np.asarray(src), np.asarray(dst), S)
     r = gamma * np.asarray(w, dtype=np.float64)
     un = row_norms(U, dual_exponent(q))
-    t = 1.0 - un / r
+    # at r = 0 the dual ball is {0}: no slack, the margin is the primal gap
+    t = np.where(r > 0, 1.0 - un / np.where(r > 0, r, 1.0), 0.0)
     return np.maximum(s, t)

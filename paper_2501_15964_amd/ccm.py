@@ -1,0 +1,314 @@
+"""ctypes binding of libccm (argument marshalling only).
+
+Each function carries the name of the C entry point it calls (include/ccm.h)
+and forwards device pointers of torch tensors plus sizes; every step of the
+computation runs in the library's HIP kernels.  The library must be built
+(paper_2501_15964_amd/_build.py); nothing here falls back to another
+implementation when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+__all__ = [
+    "CCM_SSNAL", "CCM_ADMM", "CCM_AMA",
+    "CCM_CONVERGED", "CCM_MAX_ITER", "CCM_TIMEOUT", "CCM_NUMERICAL",
+    "CcmError", "CcmOptions", "CcmStats", "lib", "library_path",
+    "ccm_version", "ccm_default_options", "ccm_build_knn_graph", "ccm_solve_path",
+    "ccm_canonical_edge_count", "ccm_op_gather", "ccm_op_project", "ccm_op_prox",
+    "ccm_op_scatter", "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy",
+    "EXPORTED_SYMBOLS",
+]
+
+CCM_SSNAL, CCM_ADMM, CCM_AMA = 0, 1, 2
+CCM_CONVERGED, CCM_MAX_ITER, CCM_TIMEOUT, CCM_NUMERICAL = 0, 1, 2, 3
+CCM_NK = 5
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libccm.so")
+
+EXPORTED_SYMBOLS = [
+    "ccm_status_string", "ccm_last_error", "ccm_version", "ccm_default_options",
+    "ccm_build_knn_graph", "ccm_solve_path", "ccm_canonical_edge_count",
+    "ccm_op_gather", "ccm_op_project", "ccm_op_prox", "ccm_op_scatter",
+    "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy",
+]
+
+
+class CcmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libccm status {status}: {msg}")
+        self.status = status
+
+
+class CcmOptions(ctypes.Structure):
+    _fields_ = [
+        ("method", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+        ("max_newton", ctypes.c_int32), ("cg_max_iter", ctypes.c_int32),
+        ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
+        ("cg_chunk", ctypes.c_int32), ("profile", ctypes.c_int32),
+        ("sigma0", ctypes.c_double), ("sigma_max", ctypes.c_double),
+        ("tau", ctypes.c_double), ("time_budget_s", ctypes.c_double),
+    ]
+
+
+class CcmStats(ctypes.Structure):
+    _fields_ = [
+        ("outer", ctypes.c_int32), ("newton", ctypes.c_int32),
+        ("cg", ctypes.c_int32), ("linesearch", ctypes.c_int32),
+        ("seconds", ctypes.c_double), ("f_p", ctypes.c_double), ("f_d", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("kern_ms", ctypes.c_double * CCM_NK), ("kern_calls", ctypes.c_int64 * CCM_NK),
+        ("edge_bytes", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return dict(outer=self.outer, newton=self.newton, cg=self.cg,
+                    linesearch=self.linesearch, seconds=self.seconds, f_p=self.f_p,
+                    f_d=self.f_d, sigma=self.sigma, kern_ms=list(self.kern_ms),
+                    kern_calls=list(self.kern_calls), edge_bytes=self.edge_bytes)
+
+
+_lib = None
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+I32 = ctypes.c_int32
+F64 = ctypes.c_double
+
+
+def lib():
+    """Load libccm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(library_path):
+        raise RuntimeError(f"{library_path} is missing: build it with "
+                           "python paper_2501_15964_amd/_build.py")
+    L = ctypes.CDLL(library_path)
+    L.ccm_status_string.restype = ctypes.c_char_p
+    L.ccm_status_string.argtypes = [I32]
+    L.ccm_last_error.restype = ctypes.c_char_p
+    L.ccm_version.restype = ctypes.c_char_p
+    L.ccm_default_options.restype = CcmOptions
+    sigs = {
+        "ccm_build_knn_graph": [P, I64, I64, I32, F64, P, P, P, I64, P, P, P],
+        "ccm_solve_path": [P, I64, I64, P, P, P, I64, P, I32, F64, F64, P, P, P, P, P, P, P, P,
+                           P, P, P],
+        "ccm_canonical_edge_count": [P, P, P, I64, I64, P, P],
+        "ccm_op_gather": [P, I64, I64, P, P, I64, P, P],
+        "ccm_op_project": [P, I64, I64, P, F64, F64, P, P],
+        "ccm_op_prox": [P, I64, I64, P, F64, F64, P, P],
+        "ccm_op_scatter": [P, I64, I64, P, P, I64, P, P],
+        "ccm_op_hess_matvec": [P, P, I64, I64, P, P, P, I64, F64, F64, F64, P, P, I32, P, P],
+        "ccm_kkt": [P, P, P, I64, I64, P, P, P, I64, F64, F64, P, P],
+        "ccm_labels": [P, P, I64, I64, P, P, I64, P, P, P],
+        "ccm_stream_copy": [P, P, I64, I32, P, P],
+    }
+    for name, args in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = I32
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != 0:
+        L = lib()
+        raise CcmError(status, f"{L.ccm_status_string(status).decode()}: "
+                               f"{L.ccm_last_error().decode()}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return P(stream.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return P(t.data_ptr())
+
+
+def _f64(t):
+    torch = _torch()
+    if t.dtype != torch.float64:
+        raise ValueError("float64 tensor expected")
+    return t
+
+
+def _i32(t):
+    torch = _torch()
+    if t.dtype != torch.int32:
+        raise ValueError("int32 tensor expected")
+    return t
+
+
+def ccm_version():
+    return lib().ccm_version().decode()
+
+
+def ccm_default_options(**kw):
+    o = lib().ccm_default_options()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def ccm_build_knn_graph(A, k, phi=0.0, m_cap=None, stream=None):
+    """k-NN Gaussian weight graph of the rows of A (device float64 [n, d]).
+    Returns (src int32 [m], dst int32 [m], w float64 [m], phi)."""
+    torch = _torch()
+    _f64(A)
+    n, d = A.shape
+    m_cap = int(m_cap if m_cap is not None else n * k)
+    src = torch.empty(max(m_cap, 1), dtype=torch.int32, device=A.device)
+    dst = torch.empty_like(src)
+    w = torch.empty(max(m_cap, 1), dtype=torch.float64, device=A.device)
+    m_out = ctypes.c_int64(0)
+    phi_out = ctypes.c_double(0.0)
+    _check(lib().ccm_build_knn_graph(_ptr(A), n, d, int(k), float(phi), _ptr(src), _ptr(dst),
+                                     _ptr(w), m_cap, ctypes.byref(m_out), ctypes.byref(phi_out),
+                                     _stream(stream)))
+    m = m_out.value
+    return src[:m], dst[:m], w[:m], phi_out.value
+
+
+def ccm_canonical_edge_count(src, dst, w, n, stream=None):
+    out = ctypes.c_int64(0)
+    _check(lib().ccm_canonical_edge_count(_ptr(_i32(src)), _ptr(_i32(dst)), _ptr(_f64(w)),
+                                          src.numel(), int(n), ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
+def ccm_solve_path(A, src, dst, w, gammas, q, tol, opts=None, want_U=False, want_labels=True,
+                   X_warm=None, U_warm=None, stream=None):
+    """Solve the clustering path.  A: device float64 [n, d]; src/dst int32
+    [m]; w float64 [m]; gammas: sequence of floats; q in {1, 2, inf}.
+    Returns a dict with X [T, n, d], U [T, m_canon, d] (if want_U), labels
+    [T, n], n_clusters, kkt [T, 4] (R_D, R_C, R_U, eta), status, stats."""
+    torch = _torch()
+    _f64(A)
+    n, d = A.shape
+    m = int(src.numel())
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+    T = int(g.size)
+    X = torch.empty((T, n, d), dtype=torch.float64, device=A.device)
+    U = None
+    if want_U:
+        mc = ccm_canonical_edge_count(src, dst, w, n, stream) if m else 0
+        U = torch.empty((T, max(mc, 1), d), dtype=torch.float64, device=A.device)[:, :mc]
+    labels = torch.empty((T, n), dtype=torch.int32, device=A.device) if want_labels else None
+    ncl = np.zeros(T, dtype=np.int32)
+    kkt = np.zeros((T, 4), dtype=np.float64)
+    status = np.zeros(T, dtype=np.int32)
+    stats = (CcmStats * max(T, 1))()
+    o = opts if opts is not None else lib().ccm_default_options()
+    _check(lib().ccm_solve_path(
+        _ptr(A), n, d, _ptr(src) if m else None, _ptr(dst) if m else None,
+        _ptr(w) if m else None, m,
+        g.ctypes.data_as(P), T, float(q), float(tol), ctypes.byref(o),
+        _ptr(X), P(U.data_ptr()) if U is not None else None,
+        _ptr(labels) if labels is not None else None,
+        ncl.ctypes.data_as(P), kkt.ctypes.data_as(P), status.ctypes.data_as(P),
+        ctypes.cast(stats, P), _ptr(X_warm), _ptr(U_warm), _stream(stream)))
+    return dict(X=X, U=U, labels=labels, n_clusters=ncl, kkt=kkt, status=status,
+                stats=[stats[t].as_dict() for t in range(T)])
+
+
+def ccm_op_gather(X, src, dst, stream=None):
+    torch = _torch()
+    n, d = X.shape
+    m = src.numel()
+    Y = torch.empty((m, d), dtype=torch.float64, device=X.device)
+    _check(lib().ccm_op_gather(_ptr(_f64(X)), n, d, _ptr(_i32(src)), _ptr(_i32(dst)), m,
+                               _ptr(Y), _stream(stream)))
+    return Y
+
+
+def ccm_op_project(Y, w, gamma, q, stream=None):
+    torch = _torch()
+    m, d = Y.shape
+    out = torch.empty_like(Y)
+    _check(lib().ccm_op_project(_ptr(_f64(Y)), m, d, _ptr(_f64(w)), float(gamma), float(q),
+                                _ptr(out), _stream(stream)))
+    return out
+
+
+def ccm_op_prox(Y, w, gamma, q, stream=None):
+    torch = _torch()
+    m, d = Y.shape
+    out = torch.empty_like(Y)
+    _check(lib().ccm_op_prox(_ptr(_f64(Y)), m, d, _ptr(_f64(w)), float(gamma), float(q),
+                             _ptr(out), _stream(stream)))
+    return out
+
+
+def ccm_op_scatter(Z, src, dst, n, stream=None):
+    torch = _torch()
+    m, d = Z.shape
+    out = torch.empty((n, d), dtype=torch.float64, device=Z.device)
+    _check(lib().ccm_op_scatter(_ptr(_f64(Z)), m, d, _ptr(_i32(src)), _ptr(_i32(dst)), int(n),
+                                _ptr(out), _stream(stream)))
+    return out
+
+
+def ccm_op_hess_matvec(X, U, src, dst, w, gamma, sigma, q, V, repeats=1, stream=None):
+    """out = V + sigma B^T P B V at Y = U + sigma B X.  Returns (out, ms)."""
+    torch = _torch()
+    n, d = X.shape
+    m = src.numel()
+    out = torch.empty_like(V)
+    ms = ctypes.c_double(0.0)
+    _check(lib().ccm_op_hess_matvec(_ptr(_f64(X)), _ptr(_f64(U)), n, d, _ptr(_i32(src)),
+                                    _ptr(_i32(dst)), _ptr(_f64(w)), m, float(gamma),
+                                    float(sigma), float(q), _ptr(_f64(V)), _ptr(out),
+                                    int(repeats), ctypes.byref(ms), _stream(stream)))
+    return out, ms.value
+
+
+def ccm_kkt(A, X, U, src, dst, w, gamma, q, stream=None):
+    """Returns dict R_D, R_C, R_U, eta, f_p, f_d, kkt."""
+    n, d = A.shape
+    m = src.numel()
+    out = np.zeros(7, dtype=np.float64)
+    _check(lib().ccm_kkt(_ptr(_f64(A)), _ptr(_f64(X)), _ptr(_f64(U)), n, d, _ptr(_i32(src)),
+                         _ptr(_i32(dst)), _ptr(_f64(w)), m, float(gamma), float(q),
+                         out.ctypes.data_as(P), _stream(stream)))
+    return dict(zip(["R_D", "R_C", "R_U", "eta", "f_p", "f_d", "kkt"], out.tolist()))
+
+
+def ccm_labels(A, X, src, dst, stream=None):
+    torch = _torch()
+    n, d = A.shape
+    m = src.numel()
+    lab = torch.empty(n, dtype=torch.int32, device=A.device)
+    nc = ctypes.c_int32(0)
+    _check(lib().ccm_labels(_ptr(_f64(A)), _ptr(_f64(X)), n, d, _ptr(_i32(src)),
+                            _ptr(_i32(dst)), m, _ptr(lab), ctypes.byref(nc), _stream(stream)))
+    return lab, nc.value
+
+
+def ccm_stream_copy(src, dst, nbytes, repeats=1, stream=None):
+    """Device copy with the library's streaming kernel; returns ms per launch."""
+    ms = ctypes.c_double(0.0)
+    _check(lib().ccm_stream_copy(P(src.data_ptr()), P(dst.data_ptr()), int(nbytes), int(repeats),
+                                 ctypes.byref(ms), _stream(stream)))
+    return ms.value

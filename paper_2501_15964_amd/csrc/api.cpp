@@ -1,0 +1,422 @@
+// C ABI entry points of libccm (declared in include/ccm.h): argument checks,
+// error reporting and dispatch to the device graph, solvers and kernels.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "knn.hpp"
+#include "solver.hpp"
+
+using namespace ccm;
+
+namespace {
+
+thread_local std::string g_err;
+
+ccm_status fail(ccm_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK_API(expr)                                                              \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(e_ == hipErrorOutOfMemory ? CCM_E_NOMEM : CCM_E_HIP,          \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));           \
+    } while (0)
+
+bool q_kind(double q, int& qk) {
+    if (q == 1.0) qk = kQ1;
+    else if (q == 2.0) qk = kQ2;
+    else if (std::isinf(q) && q > 0) qk = kQInf;
+    else return false;
+    return true;
+}
+
+ccm_status check_dims(int64_t n, int64_t d) {
+    if (n < 1) return fail(CCM_E_INVALID, "n must be >= 1");
+    if (d < 1) return fail(CCM_E_INVALID, "d must be >= 1");
+    if (!row_supported(d)) return fail(CCM_E_UNSUPPORTED, "d above 1024 is not supported");
+    if (n > (int64_t(1) << 30)) return fail(CCM_E_INVALID, "n too large");
+    return CCM_OK;
+}
+
+// finite-ness of a device array, through a host copy in chunks
+ccm_status check_finite(const double* p, int64_t count, hipStream_t s, const char* what) {
+    if (count <= 0) return CCM_OK;
+    // a device-side reduction would avoid the copy; the check runs once per call
+    const int64_t chunk = int64_t(1) << 22;
+    std::string buf;
+    double* h = nullptr;
+    if (hipHostMalloc((void**)&h, size_t(std::min(count, chunk)) * 8, hipHostMallocDefault) !=
+        hipSuccess)
+        return fail(CCM_E_NOMEM, "pinned buffer");
+    ccm_status st = CCM_OK;
+    for (int64_t o = 0; o < count && st == CCM_OK; o += chunk) {
+        const int64_t c = std::min(chunk, count - o);
+        if (hipMemcpyAsync(h, p + o, size_t(c) * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            st = fail(CCM_E_HIP, "copy for finiteness check failed");
+            break;
+        }
+        for (int64_t k = 0; k < c; ++k)
+            if (!std::isfinite(h[k])) {
+                st = fail(CCM_E_INVALID, std::string(what) + " contains NaN or Inf");
+                break;
+            }
+    }
+    (void)hipHostFree(h);
+    return st;
+}
+
+ccm_options defaults() {
+    ccm_options o;
+    std::memset(&o, 0, sizeof(o));
+    o.method = CCM_SSNAL;
+    o.max_outer = 300;
+    o.max_newton = 60;
+    o.cg_max_iter = 500;
+    o.max_iter = 20000;
+    o.check_every = 10;
+    o.cg_chunk = 8;
+    o.profile = 0;
+    o.sigma0 = 0.0;
+    o.sigma_max = 1e4;
+    o.tau = 1.618;
+    o.time_budget_s = 0.0;
+    return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ccm_status_string(ccm_status s) {
+    switch (s) {
+        case CCM_OK: return "ok";
+        case CCM_E_INVALID: return "invalid argument";
+        case CCM_E_UNSUPPORTED: return "unsupported";
+        case CCM_E_HIP: return "HIP runtime error";
+        case CCM_E_NOMEM: return "out of device memory";
+        case CCM_E_CAPACITY: return "output capacity too small";
+        default: return "unknown status";
+    }
+}
+
+const char* ccm_last_error(void) { return g_err.c_str(); }
+
+const char* ccm_version(void) { return "libccm 0.1 gfx950"; }
+
+ccm_options ccm_default_options(void) { return defaults(); }
+
+ccm_status ccm_build_knn_graph(const double* A, int64_t n, int64_t d, int32_t k, double phi,
+                               int32_t* src, int32_t* dst, double* w, int64_t m_cap,
+                               int64_t* m_out_host, double* phi_out_host, hipStream_t stream) {
+    g_err.clear();
+    if (!A || !src || !dst || !w || !m_out_host) return fail(CCM_E_INVALID, "null argument");
+    if (n < 2) return fail(CCM_E_INVALID, "n must be >= 2");
+    if (d < 1) return fail(CCM_E_INVALID, "d must be >= 1");
+    if (n > (int64_t(1) << 30) || d > (int64_t(1) << 20)) return fail(CCM_E_INVALID, "too large");
+    if (k < 1 || k > 32 || k > n - 1) return fail(CCM_E_INVALID, "need 1 <= k <= min(n - 1, 32)");
+    if (m_cap < 0) return fail(CCM_E_INVALID, "m_cap < 0");
+    if (std::isnan(phi) || std::isinf(phi)) return fail(CCM_E_INVALID, "phi must be finite");
+    ccm_status st = check_finite(A, n * d, stream, "A");
+    if (st != CCM_OK) return st;
+    std::string err;
+    int64_t mo = 0;
+    double po = 0;
+    st = knn_graph(A, n, int(d), k, phi, src, dst, w, m_cap, mo, po, stream, err);
+    *m_out_host = mo;
+    if (st != CCM_OK) return fail(st, err);
+    if (phi_out_host) *phi_out_host = po;
+    return CCM_OK;
+}
+
+ccm_status ccm_canonical_edge_count(const int32_t* src, const int32_t* dst, const double* w,
+                                    int64_t m, int64_t n, int64_t* m_canon_host,
+                                    hipStream_t stream) {
+    g_err.clear();
+    if (n < 1 || m < 0) return fail(CCM_E_INVALID, "n >= 1 and m >= 0 required");
+    if (m > 0 && (!src || !dst || !w)) return fail(CCM_E_INVALID, "null edge array");
+    if (!m_canon_host) return fail(CCM_E_INVALID, "null m_canon_host");
+    std::string err;
+    int64_t mc = 0;
+    ccm_status st = graph_canonical_count(src, dst, w, m, n, stream, mc, err);
+    if (st != CCM_OK) return fail(st, err);
+    *m_canon_host = mc;
+    return CCM_OK;
+}
+
+ccm_status ccm_solve_path(const double* A, int64_t n, int64_t d, const int32_t* src,
+                          const int32_t* dst, const double* w, int64_t m,
+                          const double* gammas_host, int32_t n_gamma, double q, double tol,
+                          const ccm_options* opts, double* X_out, double* U_out,
+                          int32_t* labels_out, int32_t* n_clusters_host, double* kkt_host,
+                          int32_t* status_host, ccm_stats* stats_host, const double* X_warm,
+                          const double* U_warm, hipStream_t stream) {
+    g_err.clear();
+    ccm_status st = check_dims(n, d);
+    if (st != CCM_OK) return st;
+    if (!A) return fail(CCM_E_INVALID, "A is null");
+    if (!X_out) return fail(CCM_E_INVALID, "X_out is null");
+    if (m < 0) return fail(CCM_E_INVALID, "m < 0");
+    if (m > 0 && (!src || !dst || !w)) return fail(CCM_E_INVALID, "null edge array");
+    if (n_gamma < 0 || (n_gamma > 0 && !gammas_host))
+        return fail(CCM_E_INVALID, "bad gamma list");
+    for (int t = 0; t < n_gamma; ++t)
+        if (!std::isfinite(gammas_host[t]) || gammas_host[t] < 0)
+            return fail(CCM_E_INVALID, "gamma values must be finite and >= 0");
+    int qk = 0;
+    if (!q_kind(q, qk)) return fail(CCM_E_UNSUPPORTED, "q must be 1, 2 or inf");
+    if (!(tol > 0) || !std::isfinite(tol)) return fail(CCM_E_INVALID, "tol must be > 0");
+    ccm_options o = opts ? *opts : defaults();
+    if (o.method != CCM_SSNAL && o.method != CCM_ADMM && o.method != CCM_AMA)
+        return fail(CCM_E_INVALID, "unknown method");
+    if (o.max_outer < 1 || o.max_newton < 1 || o.cg_max_iter < 1 || o.max_iter < 1)
+        return fail(CCM_E_INVALID, "iteration limits must be >= 1");
+    if (o.sigma0 <= 0) o.sigma0 = (o.method == CCM_SSNAL) ? 10.0 : 1.0;
+    if (!(o.sigma_max >= o.sigma0)) o.sigma_max = o.sigma0;
+    if (!(o.tau > 0 && o.tau < 1.6181)) return fail(CCM_E_INVALID, "tau must be in (0, 1.618]");
+    st = check_finite(A, n * d, stream, "A");
+    if (st != CCM_OK) return st;
+    if (n_gamma == 0) return CCM_OK;
+    std::string err;
+    OwnedGraph og;
+    st = graph_build(src, dst, w, m, n, false, stream, og, err);
+    if (st != CCM_OK) return fail(st, err);
+    Solver solver(og.g, int(d), qk, A, stream, o, tol, err);
+    st = solver.run_path(gammas_host, n_gamma, X_warm, U_warm, X_out, U_out, labels_out,
+                         n_clusters_host, kkt_host, status_host, stats_host);
+    if (st != CCM_OK) return fail(st, err);
+    HIPCHK_API(hipStreamSynchronize(stream));
+    return CCM_OK;
+}
+
+ccm_status ccm_op_gather(const double* X, int64_t n, int64_t d, const int32_t* src,
+                         const int32_t* dst, int64_t m, double* Y, hipStream_t stream) {
+    g_err.clear();
+    ccm_status st = check_dims(n, d);
+    if (st != CCM_OK) return st;
+    if (m < 0) return fail(CCM_E_INVALID, "m < 0");
+    if (m == 0) return CCM_OK;
+    DevGraph g;
+    g.n = n;
+    g.m = m;
+    g.src = src;
+    g.dst = dst;
+    launch_gather(g, int(d), X, Y, stream);
+    HIPCHK_API(hipGetLastError());
+    return CCM_OK;
+}
+
+ccm_status ccm_op_project(const double* Y, int64_t m, int64_t d, const double* w, double gamma,
+                          double q, double* Pi, hipStream_t stream) {
+    g_err.clear();
+    int qk = 0;
+    if (!q_kind(q, qk)) return fail(CCM_E_UNSUPPORTED, "q must be 1, 2 or inf");
+    if (m < 0 || d < 1 || !row_supported(d)) return fail(CCM_E_INVALID, "bad sizes");
+    if (!(gamma >= 0) || !std::isfinite(gamma)) return fail(CCM_E_INVALID, "bad gamma");
+    if (m == 0) return CCM_OK;
+    launch_project(m, int(d), qk, Y, w, gamma, false, Pi, stream);
+    HIPCHK_API(hipGetLastError());
+    return CCM_OK;
+}
+
+ccm_status ccm_op_prox(const double* Y, int64_t m, int64_t d, const double* w, double gamma,
+                       double q, double* Z, hipStream_t stream) {
+    g_err.clear();
+    int qk = 0;
+    if (!q_kind(q, qk)) return fail(CCM_E_UNSUPPORTED, "q must be 1, 2 or inf");
+    if (m < 0 || d < 1 || !row_supported(d)) return fail(CCM_E_INVALID, "bad sizes");
+    if (!(gamma >= 0) || !std::isfinite(gamma)) return fail(CCM_E_INVALID, "bad gamma");
+    if (m == 0) return CCM_OK;
+    launch_project(m, int(d), qk, Y, w, gamma, true, Z, stream);
+    HIPCHK_API(hipGetLastError());
+    return CCM_OK;
+}
+
+ccm_status ccm_op_scatter(const double* Z, int64_t m, int64_t d, const int32_t* src,
+                          const int32_t* dst, int64_t n, double* out, hipStream_t stream) {
+    g_err.clear();
+    ccm_status st = check_dims(n, d);
+    if (st != CCM_OK) return st;
+    std::string err;
+    OwnedGraph og;
+    std::vector<double> ones;
+    DevMem wbuf;
+    // unit weights: only the incidence structure is used
+    if (m > 0) {
+        HIPCHK_API(wbuf.alloc(size_t(m) * 8, stream));
+        launch_fill(wbuf.as<double>(), m, 1.0, stream);
+    }
+    st = graph_build(src, dst, wbuf.as<double>(), m, n, true, stream, og, err);
+    if (st != CCM_OK) return fail(st, err);
+    DevMem part;
+    HIPCHK_API(part.alloc(size_t(kMaxGrid) * kScatterNV * 8, stream));
+    launch_scatter(og.g, int(d), kQ2, 0.0, nullptr, 0.0, nullptr, 1.0, Z, out, false, Payload{},
+                   0.0, 0.0, nullptr, part.as<double>(), stream);
+    HIPCHK_API(hipGetLastError());
+    HIPCHK_API(hipStreamSynchronize(stream));
+    return CCM_OK;
+}
+
+ccm_status ccm_op_hess_matvec(const double* X, const double* U, int64_t n, int64_t d,
+                              const int32_t* src, const int32_t* dst, const double* w, int64_t m,
+                              double gamma, double sigma, double q, const double* V, double* out,
+                              int32_t repeats, double* ms_host, hipStream_t stream) {
+    g_err.clear();
+    ccm_status st = check_dims(n, d);
+    if (st != CCM_OK) return st;
+    int qk = 0;
+    if (!q_kind(q, qk)) return fail(CCM_E_UNSUPPORTED, "q must be 1, 2 or inf");
+    if (!(sigma > 0) || !(gamma >= 0)) return fail(CCM_E_INVALID, "sigma > 0, gamma >= 0");
+    if (repeats < 1) return fail(CCM_E_INVALID, "repeats >= 1");
+    std::string err;
+    OwnedGraph og;
+    st = graph_build(src, dst, w, m, n, true, stream, og, err);
+    if (st != CCM_OK) return fail(st, err);
+    const int64_t M = m * d;
+    DevMem Pi, al, bi, cn, part;
+    HIPCHK_API(Pi.alloc(size_t(M) * 8, stream));
+    HIPCHK_API(al.alloc(size_t(m) * 8, stream));
+    HIPCHK_API(bi.alloc(size_t(m) * mask_words(int(d)) * 16, stream));
+    HIPCHK_API(cn.alloc(size_t(m) * 4, stream));
+    HIPCHK_API(part.alloc(size_t(kMaxGrid) * 8 * 8, stream));
+    Payload pl{al.as<double>(), bi.as<uint64_t>(), cn.as<int>()};
+    if (m > 0)
+        launch_edge_ssnal(og.g, int(d), qk, gamma, sigma, X, U, Pi.as<double>(), pl,
+                          part.as<double>(), stream);
+    hipEvent_t e0, e1;
+    HIPCHK_API(hipEventCreate(&e0));
+    HIPCHK_API(hipEventCreate(&e1));
+    HIPCHK_API(hipEventRecord(e0, stream));
+    for (int r = 0; r < repeats; ++r)
+        launch_matvec(og.g, int(d), qk, 0, V, Pi.as<double>(), pl, gamma, sigma, 1.0, nullptr, out,
+                      part.as<double>(), CgSkip{}, stream);
+    HIPCHK_API(hipEventRecord(e1, stream));
+    HIPCHK_API(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK_API(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (ms_host) *ms_host = double(ms) / repeats;
+    HIPCHK_API(hipGetLastError());
+    HIPCHK_API(hipStreamSynchronize(stream));
+    return CCM_OK;
+}
+
+ccm_status ccm_kkt(const double* A, const double* X, const double* U, int64_t n, int64_t d,
+                   const int32_t* src, const int32_t* dst, const double* w, int64_t m,
+                   double gamma, double q, double* out_host, hipStream_t stream) {
+    g_err.clear();
+    ccm_status st = check_dims(n, d);
+    if (st != CCM_OK) return st;
+    int qk = 0;
+    if (!q_kind(q, qk)) return fail(CCM_E_UNSUPPORTED, "q must be 1, 2 or inf");
+    if (!out_host) return fail(CCM_E_INVALID, "out_host is null");
+    std::string err;
+    OwnedGraph og;
+    st = graph_build(src, dst, w, m, n, true, stream, og, err);
+    if (st != CCM_OK) return fail(st, err);
+    const int64_t N = n * d, M = m * d;
+    DevMem Uf, G, p1, p2, p3, sc;
+    HIPCHK_API(Uf.alloc(size_t(M) * 8, stream));
+    HIPCHK_API(G.alloc(size_t(N) * 8, stream));
+    HIPCHK_API(p1.alloc(size_t(kMaxGrid) * 8 * 8, stream));
+    HIPCHK_API(p2.alloc(size_t(kMaxGrid) * 8 * 8, stream));
+    HIPCHK_API(p3.alloc(size_t(kMaxGrid) * 8 * 8, stream));
+    HIPCHK_API(sc.alloc(32 * 8, stream));
+    double* s = sc.as<double>();
+    // KKT edge pass on (X, U), writing Pi_C(U) for the dual objective
+    int gp = launch_edge_kkt(og.g, int(d), qk, gamma, X, U, Uf.as<double>(), p1.as<double>(),
+                             stream);
+    launch_finalize(p1.as<double>(), gp, kEdgeKktNV, s + 0, stream);
+    // R_D with U as given
+    gp = launch_scatter(og.g, int(d), qk, 1.0, X, -1.0, A, 1.0, U, G.as<double>(), false,
+                        Payload{}, gamma, 0.0, nullptr, p2.as<double>(), stream);
+    launch_finalize(p2.as<double>(), gp, kScatterNV, s + 8, stream);
+    // f_d at Pi_C(U)
+    gp = launch_scatter(og.g, int(d), qk, 0.0, nullptr, 1.0, A, 1.0, Uf.as<double>(),
+                        G.as<double>(), false, Payload{}, gamma, 0.0, nullptr, p3.as<double>(),
+                        stream);
+    launch_finalize(p3.as<double>(), gp, kScatterNV, s + 16, stream);
+    // ||A||^2 for the R_D denominator
+    gp = launch_dot(A, A, N, p1.as<double>(), stream);
+    launch_finalize(p1.as<double>(), gp, 1, s + 24, stream);
+    double h[32];
+    HIPCHK_API(hipMemcpyAsync(h, s, sizeof(h), hipMemcpyDeviceToHost, stream));
+    HIPCHK_API(hipStreamSynchronize(stream));
+    const double nA = std::sqrt(h[24]);
+    const double nbx = std::sqrt(h[1]), nu = std::sqrt(h[2]);
+    const double RD = std::sqrt(h[8]) / (1.0 + nA);
+    const double RC = std::sqrt(h[0]) / (1.0 + nbx + nu);
+    const double RU = std::sqrt(h[3]) / (1.0 + nu);
+    const double fp = h[9] + h[4];
+    const double fd = h[18] - 0.5 * h[19];
+    out_host[0] = RD;
+    out_host[1] = RC;
+    out_host[2] = RU;
+    out_host[3] = std::fabs(fp - fd) / (1.0 + std::fabs(fp) + std::fabs(fd));
+    out_host[4] = fp;
+    out_host[5] = fd;
+    out_host[6] = std::max(RD, std::max(RC, RU));
+    return CCM_OK;
+}
+
+ccm_status ccm_labels(const double* A, const double* X, int64_t n, int64_t d,
+                      const int32_t* src, const int32_t* dst, int64_t m, int32_t* labels,
+                      int32_t* n_clusters_host, hipStream_t stream) {
+    g_err.clear();
+    ccm_status st = check_dims(n, d);
+    if (st != CCM_OK) return st;
+    if (m < 0) return fail(CCM_E_INVALID, "m < 0");
+    DevGraph g;
+    g.n = n;
+    g.m = m;
+    g.src = src;
+    g.dst = dst;
+    DevMem work, sp, fused, parent, rank, temp, nc;
+    HIPCHK_API(work.alloc(size_t(spread_work_size(n, int(d))) * 8, stream));
+    HIPCHK_API(sp.alloc(8, stream));
+    launch_spread(A, n, int(d), work.as<double>(), sp.as<double>(), stream);
+    double S = 0;
+    HIPCHK_API(hipMemcpyAsync(&S, sp.p, 8, hipMemcpyDeviceToHost, stream));
+    HIPCHK_API(hipStreamSynchronize(stream));
+    HIPCHK_API(fused.alloc(size_t(std::max<int64_t>(m, 1)) * 4, stream));
+    HIPCHK_API(parent.alloc(size_t(n) * 4, stream));
+    HIPCHK_API(rank.alloc(size_t(n + 1) * 4, stream));
+    const size_t tb = labels_temp_bytes(n);
+    HIPCHK_API(temp.alloc(tb, stream));
+    HIPCHK_API(nc.alloc(4, stream));
+    if (m > 0) launch_fused_flags(g, int(d), X, 1e-5 * (1.0 + S), fused.as<int>(), stream);
+    launch_labels(n, m, src, dst, fused.as<int>(), parent.as<int>(), rank.as<int>(), temp.p, tb,
+                  labels, nc.as<int>(), stream);
+    int h = 0;
+    HIPCHK_API(hipMemcpyAsync(&h, nc.p, 4, hipMemcpyDeviceToHost, stream));
+    HIPCHK_API(hipStreamSynchronize(stream));
+    if (n_clusters_host) *n_clusters_host = h;
+    return CCM_OK;
+}
+
+ccm_status ccm_stream_copy(const void* src, void* dst, int64_t bytes, int32_t repeats,
+                           double* ms_host, hipStream_t stream) {
+    g_err.clear();
+    if (bytes < 0 || repeats < 1) return fail(CCM_E_INVALID, "bytes >= 0, repeats >= 1");
+    hipEvent_t e0, e1;
+    HIPCHK_API(hipEventCreate(&e0));
+    HIPCHK_API(hipEventCreate(&e1));
+    HIPCHK_API(hipEventRecord(e0, stream));
+    for (int r = 0; r < repeats; ++r) launch_stream_copy(src, dst, bytes, stream);
+    HIPCHK_API(hipEventRecord(e1, stream));
+    HIPCHK_API(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK_API(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (ms_host) *ms_host = double(ms) / repeats;
+    return CCM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,523 @@
+// Edge-parallel kernels: the gather B X, the per-edge projection onto the dual
+// ball C_l = {||u||_{q*} <= r_l} (r_l = gamma w_l), the prox of
+// r_l ||.||_q by the Moreau identity prox = id - Pi, and the generalized
+// Jacobian payload of Pi_C used by the SSNAL Newton matvec.
+//
+// Layout: edges are rows of an m x d FP64 array in canonical order
+// (src < dst, sorted), so edge l's row sits next to edge l+1's and a row
+// group of LPR lanes streams it with unit-stride 8-byte loads; the endpoint
+// rows x_src, x_dst are gathered from the n x d vertex array.
+#include "launch.hpp"
+
+namespace ccm {
+namespace {
+
+// Per-edge projection of y (held in registers, NPER values per lane) onto
+// the dual ball of radius r, with the Jacobian payload.
+template <int LPR, int NPER, int Q>
+struct RowProj {
+    double pi[NPER];
+    double alpha = 1.0;    // q = 2
+    int cnt = -1;          // q = inf
+    uint64_t m1[NPER];     // q = 1: |y_k| <= r; q = inf: k in support
+    uint64_t m2[NPER];     // q = inf: y_k < 0
+};
+
+template <int LPR, int NPER, int Q, bool BITS>
+__device__ __forceinline__ void project_row(const double (&y)[NPER], int gl, int lane, int d,
+                                            double r, RowProj<LPR, NPER, Q>& o) {
+    if constexpr (Q == kQ2) {
+        // l2 ball: scale y by min(1, r / ||y||); the boundary counts as inside
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) s += y[t] * y[t];
+        s = group_sum<LPR>(s);
+        const double nrm = sqrt(s);
+        if (nrm > r) {
+            const double a = r / nrm;
+            o.alpha = a;
+#pragma unroll
+            for (int t = 0; t < NPER; ++t) o.pi[t] = y[t] * a;
+        } else {
+            o.alpha = 1.0;
+#pragma unroll
+            for (int t = 0; t < NPER; ++t) o.pi[t] = y[t];
+        }
+    } else if constexpr (Q == kQ1) {
+        // l_inf ball (box): clamp each coordinate to [-r, r]
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            o.pi[t] = fmin(fmax(y[t], -r), r);
+            if constexpr (BITS) {
+                const bool valid = gl + LPR * t < d;
+                o.m1[t] = group_bits<LPR>(__ballot(valid && fabs(y[t]) <= r), lane);
+            }
+        }
+    } else {
+        // l1 ball by support pruning (Michelot 1986): theta from the current
+        // support, drop coordinates with |y_k| <= theta, repeat until the
+        // support is stable; then Pi_k = sign(y_k) (|y_k| - theta)_+.
+        double v[NPER];
+        double s = 0.0;
+        int c = 0;
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            v[t] = fabs(y[t]);
+            s += v[t];
+            c += (gl + LPR * t < d) ? 1 : 0;
+        }
+        s = group_sum<LPR>(s);
+        if (s <= r) {
+            o.cnt = -1;
+#pragma unroll
+            for (int t = 0; t < NPER; ++t) {
+                o.pi[t] = y[t];
+                if constexpr (BITS) { o.m1[t] = 0; o.m2[t] = 0; }
+            }
+        } else if (!(r > 0.0)) {
+            o.cnt = 0;
+#pragma unroll
+            for (int t = 0; t < NPER; ++t) {
+                o.pi[t] = 0.0;
+                if constexpr (BITS) { o.m1[t] = 0; o.m2[t] = 0; }
+            }
+        } else {
+            int cc = group_sum_i<LPR>(c);
+            double theta = (s - r) / double(cc);
+            for (int it = 0; it <= d; ++it) {
+                double s2 = 0.0;
+                int c2 = 0;
+#pragma unroll
+                for (int t = 0; t < NPER; ++t) {
+                    if (v[t] > theta) { s2 += v[t]; ++c2; }
+                }
+                s2 = group_sum<LPR>(s2);
+                c2 = group_sum_i<LPR>(c2);
+                if (c2 == cc) break;
+                cc = c2;
+                theta = (s2 - r) / double(c2);
+            }
+            o.cnt = cc;
+#pragma unroll
+            for (int t = 0; t < NPER; ++t) {
+                const double mag = fmax(v[t] - theta, 0.0);
+                o.pi[t] = copysign(mag, y[t]);
+                if constexpr (BITS) {
+                    const bool valid = gl + LPR * t < d;
+                    o.m1[t] = group_bits<LPR>(__ballot(valid && v[t] > theta), lane);
+                    o.m2[t] = group_bits<LPR>(__ballot(valid && y[t] < 0.0), lane);
+                }
+            }
+        }
+    }
+}
+
+template <int LPR, int NPER, int Q>
+__device__ __forceinline__ void store_payload(const RowProj<LPR, NPER, Q>& o, int64_t l, int gl,
+                                              int d, Payload pl) {
+    if (gl != 0) return;
+    if constexpr (Q == kQ2) {
+        pl.alpha[l] = o.alpha;
+    } else {
+        const int W = (d + LPR - 1) / LPR;
+        constexpr int NB = (Q == kQ1) ? 1 : 2;
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            if (t < W) {
+                pl.bits[(l * W + t) * NB] = o.m1[t];
+                if constexpr (Q == kQInf) pl.bits[(l * W + t) * NB + 1] = o.m2[t];
+            }
+        }
+        if constexpr (Q == kQInf) pl.cnt[l] = o.cnt;
+    }
+}
+
+template <int LPR, int NPER, int Q>
+__global__ __launch_bounds__(kBlock) void k_edge_ssnal(int64_t m, int d, const int* __restrict__ src,
+                                                       const int* __restrict__ dst,
+                                                       const double* __restrict__ w, double gamma,
+                                                       double sigma, const double* __restrict__ X,
+                                                       const double* __restrict__ U,
+                                                       double* __restrict__ Pi, Payload pl,
+                                                       double* __restrict__ partials) {
+    const int lane = threadIdx.x & 63;
+    const int gl = lane % LPR;
+    constexpr int GPB = kBlock / LPR;
+    double acc[kEdgeSsnalNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t l = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; l < m;
+         l += int64_t(gridDim.x) * GPB) {
+        const int64_t i = src[l], j = dst[l];
+        const double r = gamma * w[l];
+        double y[NPER], bx[NPER], u[NPER];
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            if (k < d) {
+                bx[t] = X[i * d + k] - X[j * d + k];
+                u[t] = U[l * d + k];
+            } else {
+                bx[t] = 0.0;
+                u[t] = 0.0;
+            }
+            y[t] = u[t] + sigma * bx[t];
+        }
+        RowProj<LPR, NPER, Q> o;
+        project_row<LPR, NPER, Q, true>(y, gl, lane, d, r, o);
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            if (k < d) {
+                Pi[l * d + k] = o.pi[t];
+                const double e = o.pi[t] - u[t];
+                acc[0] += bx[t] * o.pi[t];
+                acc[1] += e * e;
+                acc[2] += bx[t] * bx[t];
+                acc[3] += o.pi[t] * o.pi[t];
+            }
+        }
+        store_payload<LPR, NPER, Q>(o, l, gl, d, pl);
+        if (gl == 0) {
+            if constexpr (Q == kQ2) acc[4] += (o.alpha < 1.0) ? 1.0 : 0.0;
+            else if constexpr (Q == kQInf) acc[4] += (o.cnt >= 0) ? 1.0 : 0.0;
+            else acc[4] += 1.0;
+        }
+    }
+    block_reduce_store<kEdgeSsnalNV>(acc, partials + blockIdx.x * kEdgeSsnalNV);
+}
+
+template <int LPR, int NPER, int Q>
+__global__ __launch_bounds__(kBlock) void k_edge_kkt(int64_t m, int d, const int* __restrict__ src,
+                                                     const int* __restrict__ dst,
+                                                     const double* __restrict__ w, double gamma,
+                                                     const double* __restrict__ X,
+                                                     const double* __restrict__ U,
+                                                     double* __restrict__ Ufeas,
+                                                     double* __restrict__ partials) {
+    const int lane = threadIdx.x & 63;
+    const int gl = lane % LPR;
+    constexpr int GPB = kBlock / LPR;
+    double acc[kEdgeKktNV] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t l = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; l < m;
+         l += int64_t(gridDim.x) * GPB) {
+        const int64_t i = src[l], j = dst[l];
+        const double r = gamma * w[l];
+        double bx[NPER], u[NPER], v[NPER];
+        double nq = 0.0;
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            if (k < d) {
+                bx[t] = X[i * d + k] - X[j * d + k];
+                u[t] = U[l * d + k];
+            } else {
+                bx[t] = 0.0;
+                u[t] = 0.0;
+            }
+            v[t] = bx[t] + u[t];
+            if constexpr (Q == kQ1) nq += fabs(bx[t]);
+            else if constexpr (Q == kQ2) nq += bx[t] * bx[t];
+            else nq = fmax(nq, fabs(bx[t]));
+        }
+        if constexpr (Q == kQ2) {
+            nq = group_sum<LPR>(nq);
+            if (gl == 0) acc[4] += r * sqrt(nq);
+        } else if constexpr (Q == kQInf) {
+            nq = group_max<LPR>(nq);
+            if (gl == 0) acc[4] += r * nq;
+        } else {
+            acc[4] += r * nq;
+        }
+        RowProj<LPR, NPER, Q> pv, pu;
+        project_row<LPR, NPER, Q, false>(v, gl, lane, d, r, pv);
+        project_row<LPR, NPER, Q, false>(u, gl, lane, d, r, pu);
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            if (k < d) {
+                const double e = pv.pi[t] - u[t];
+                const double f = u[t] - pu.pi[t];
+                acc[0] += e * e;
+                acc[1] += bx[t] * bx[t];
+                acc[2] += u[t] * u[t];
+                acc[3] += f * f;
+                if (Ufeas) Ufeas[l * d + k] = pu.pi[t];
+            }
+        }
+    }
+    block_reduce_store<kEdgeKktNV>(acc, partials + blockIdx.x * kEdgeKktNV);
+}
+
+template <int LPR, int NPER, int Q>
+__global__ __launch_bounds__(kBlock) void k_edge_admm(int64_t m, int d, const int* __restrict__ src,
+                                                      const int* __restrict__ dst,
+                                                      const double* __restrict__ w, double gamma,
+                                                      double sigma, double tau,
+                                                      const double* __restrict__ X,
+                                                      double* __restrict__ Z,
+                                                      double* __restrict__ L,
+                                                      double* __restrict__ Qo,
+                                                      double* __restrict__ Uf,
+                                                      double* __restrict__ partials) {
+    const int lane = threadIdx.x & 63;
+    const int gl = lane % LPR;
+    constexpr int GPB = kBlock / LPR;
+    double acc[kEdgeAdmmNV] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t l = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; l < m;
+         l += int64_t(gridDim.x) * GPB) {
+        const int64_t i = src[l], j = dst[l];
+        const double r = gamma * w[l];
+        double bx[NPER], lam[NPER], zo[NPER], y[NPER];
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            if (k < d) {
+                bx[t] = X[i * d + k] - X[j * d + k];
+                lam[t] = L[l * d + k];
+                zo[t] = Z[l * d + k];
+            } else {
+                bx[t] = lam[t] = zo[t] = 0.0;
+            }
+            y[t] = sigma * bx[t] + lam[t];
+        }
+        RowProj<LPR, NPER, Q> o;
+        project_row<LPR, NPER, Q, false>(y, gl, lane, d, r, o);
+        double ln[NPER];
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            const double zn = bx[t] + (lam[t] - o.pi[t]) / sigma;
+            ln[t] = lam[t] + tau * sigma * (bx[t] - zn);
+            if (k < d) {
+                Z[l * d + k] = zn;
+                L[l * d + k] = ln[t];
+                Qo[l * d + k] = sigma * zn - ln[t];
+                const double rp = bx[t] - zn, dz = zn - zo[t];
+                acc[0] += rp * rp;
+                acc[1] += dz * dz;
+                acc[2] += bx[t] * bx[t];
+                acc[3] += zn * zn;
+            }
+        }
+        if (Uf) {
+            RowProj<LPR, NPER, Q> pu;
+            project_row<LPR, NPER, Q, false>(ln, gl, lane, d, r, pu);
+#pragma unroll
+            for (int t = 0; t < NPER; ++t) {
+                const int k = gl + LPR * t;
+                if (k < d) Uf[l * d + k] = pu.pi[t];
+            }
+        }
+    }
+    block_reduce_store<kEdgeAdmmNV>(acc, partials + blockIdx.x * kEdgeAdmmNV);
+}
+
+template <int LPR, int NPER, int Q>
+__global__ __launch_bounds__(kBlock) void k_edge_ama(int64_t m, int d, const int* __restrict__ src,
+                                                     const int* __restrict__ dst,
+                                                     const double* __restrict__ w, double gamma,
+                                                     double nu, double beta,
+                                                     const double* __restrict__ X,
+                                                     double* __restrict__ U,
+                                                     double* __restrict__ V,
+                                                     double* __restrict__ partials) {
+    const int lane = threadIdx.x & 63;
+    const int gl = lane % LPR;
+    constexpr int GPB = kBlock / LPR;
+    double acc[kEdgeAmaNV] = {0.0, 0.0};
+    for (int64_t l = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; l < m;
+         l += int64_t(gridDim.x) * GPB) {
+        const int64_t i = src[l], j = dst[l];
+        const double r = gamma * w[l];
+        double y[NPER], vo[NPER], uo[NPER];
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            if (k < d) {
+                vo[t] = V[l * d + k];
+                uo[t] = U[l * d + k];
+                y[t] = vo[t] + nu * (X[i * d + k] - X[j * d + k]);
+            } else {
+                vo[t] = uo[t] = y[t] = 0.0;
+            }
+        }
+        RowProj<LPR, NPER, Q> o;
+        project_row<LPR, NPER, Q, false>(y, gl, lane, d, r, o);
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            if (k < d) {
+                const double un = o.pi[t];
+                const double du = un - uo[t];
+                acc[0] += (vo[t] - un) * du;
+                acc[1] += du * du;
+                U[l * d + k] = un;
+                V[l * d + k] = un + beta * du;
+            }
+        }
+    }
+    block_reduce_store<kEdgeAmaNV>(acc, partials + blockIdx.x * kEdgeAmaNV);
+}
+
+template <int LPR, int NPER>
+__global__ __launch_bounds__(kBlock) void k_gather(int64_t m, int d, const int* __restrict__ src,
+                                                   const int* __restrict__ dst,
+                                                   const double* __restrict__ X,
+                                                   double* __restrict__ Y) {
+    const int gl = (threadIdx.x & 63) % LPR;
+    constexpr int GPB = kBlock / LPR;
+    for (int64_t l = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; l < m;
+         l += int64_t(gridDim.x) * GPB) {
+        const int64_t i = src[l], j = dst[l];
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            if (k < d) Y[l * d + k] = X[i * d + k] - X[j * d + k];
+        }
+    }
+}
+
+template <int LPR, int NPER, int Q>
+__global__ __launch_bounds__(kBlock) void k_project(int64_t m, int d, const double* __restrict__ Y,
+                                                    const double* __restrict__ w, double gamma,
+                                                    int prox, double* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int gl = lane % LPR;
+    constexpr int GPB = kBlock / LPR;
+    for (int64_t l = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; l < m;
+         l += int64_t(gridDim.x) * GPB) {
+        const double r = gamma * w[l];
+        double y[NPER];
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            y[t] = (k < d) ? Y[l * d + k] : 0.0;
+        }
+        RowProj<LPR, NPER, Q> o;
+        project_row<LPR, NPER, Q, false>(y, gl, lane, d, r, o);
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            if (k < d) out[l * d + k] = prox ? (y[t] - o.pi[t]) : o.pi[t];
+        }
+    }
+}
+
+template <int LPR, int NPER>
+__global__ __launch_bounds__(kBlock) void k_fused_flags(int64_t m, int d,
+                                                        const int* __restrict__ src,
+                                                        const int* __restrict__ dst,
+                                                        const double* __restrict__ X, double thr,
+                                                        int* __restrict__ fused) {
+    const int gl = (threadIdx.x & 63) % LPR;
+    constexpr int GPB = kBlock / LPR;
+    for (int64_t l = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; l < m;
+         l += int64_t(gridDim.x) * GPB) {
+        const int64_t i = src[l], j = dst[l];
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            if (k < d) {
+                const double e = X[i * d + k] - X[j * d + k];
+                s += e * e;
+            }
+        }
+        s = group_sum<LPR>(s);
+        if (gl == 0) fused[l] = sqrt(s) <= thr ? 1 : 0;
+    }
+}
+
+}  // namespace
+
+int launch_edge_ssnal(const DevGraph& g, int d, int qk, double gamma, double sigma,
+                      const double* X, const double* U, double* Pi, Payload pl,
+                      double* partials, hipStream_t s) {
+    int grid = 1;
+    dispatch_row(d, [&](auto L, auto N) {
+        constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
+        grid = row_grid(g.m, lpr);
+        dispatch_q(qk, [&](auto Qc) {
+            constexpr int q = decltype(Qc)::value;
+            hipLaunchKernelGGL((k_edge_ssnal<lpr, nper, q>), dim3(grid), dim3(kBlock), 0, s, g.m,
+                               d, g.src, g.dst, g.w, gamma, sigma, X, U, Pi, pl, partials);
+        });
+    });
+    return grid;
+}
+
+int launch_edge_kkt(const DevGraph& g, int d, int qk, double gamma, const double* X,
+                    const double* U, double* Ufeas, double* partials, hipStream_t s) {
+    int grid = 1;
+    dispatch_row(d, [&](auto L, auto N) {
+        constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
+        grid = row_grid(g.m, lpr);
+        dispatch_q(qk, [&](auto Qc) {
+            constexpr int q = decltype(Qc)::value;
+            hipLaunchKernelGGL((k_edge_kkt<lpr, nper, q>), dim3(grid), dim3(kBlock), 0, s, g.m, d,
+                               g.src, g.dst, g.w, gamma, X, U, Ufeas, partials);
+        });
+    });
+    return grid;
+}
+
+int launch_edge_admm(const DevGraph& g, int d, int qk, double gamma, double sigma, double tau,
+                     const double* X, double* Z, double* L_, double* Q, double* Uf,
+                     double* partials, hipStream_t s) {
+    int grid = 1;
+    dispatch_row(d, [&](auto L, auto N) {
+        constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
+        grid = row_grid(g.m, lpr);
+        dispatch_q(qk, [&](auto Qc) {
+            constexpr int q = decltype(Qc)::value;
+            hipLaunchKernelGGL((k_edge_admm<lpr, nper, q>), dim3(grid), dim3(kBlock), 0, s, g.m,
+                               d, g.src, g.dst, g.w, gamma, sigma, tau, X, Z, L_, Q, Uf, partials);
+        });
+    });
+    return grid;
+}
+
+int launch_edge_ama(const DevGraph& g, int d, int qk, double gamma, double nu, double beta,
+                    const double* X, double* U, double* V, double* partials, hipStream_t s) {
+    int grid = 1;
+    dispatch_row(d, [&](auto L, auto N) {
+        constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
+        grid = row_grid(g.m, lpr);
+        dispatch_q(qk, [&](auto Qc) {
+            constexpr int q = decltype(Qc)::value;
+            hipLaunchKernelGGL((k_edge_ama<lpr, nper, q>), dim3(grid), dim3(kBlock), 0, s, g.m, d,
+                               g.src, g.dst, g.w, gamma, nu, beta, X, U, V, partials);
+        });
+    });
+    return grid;
+}
+
+void launch_gather(const DevGraph& g, int d, const double* X, double* Y, hipStream_t s) {
+    dispatch_row(d, [&](auto L, auto N) {
+        constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
+        hipLaunchKernelGGL((k_gather<lpr, nper>), dim3(row_grid(g.m, lpr)), dim3(kBlock), 0, s,
+                           g.m, d, g.src, g.dst, X, Y);
+    });
+}
+
+void launch_project(int64_t m, int d, int qk, const double* Y, const double* w, double gamma,
+                    bool prox, double* out, hipStream_t s) {
+    dispatch_row(d, [&](auto L, auto N) {
+        constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
+        dispatch_q(qk, [&](auto Qc) {
+            constexpr int q = decltype(Qc)::value;
+            hipLaunchKernelGGL((k_project<lpr, nper, q>), dim3(row_grid(m, lpr)), dim3(kBlock), 0,
+                               s, m, d, Y, w, gamma, prox ? 1 : 0, out);
+        });
+    });
+}
+
+void launch_fused_flags(const DevGraph& g, int d, const double* X, double thr, int* fused,
+                        hipStream_t s) {
+    dispatch_row(d, [&](auto L, auto N) {
+        constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
+        hipLaunchKernelGGL((k_fused_flags<lpr, nper>), dim3(row_grid(g.m, lpr)), dim3(kBlock), 0,
+                           s, g.m, d, g.src, g.dst, X, thr, fused);
+    });
+}
+
+}  // namespace ccm

@@ -1,0 +1,262 @@
+// Device graph construction (see graph.hpp).
+#include <hipcub/hipcub.hpp>
+
+#include "graph.hpp"
+
+namespace ccm {
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_validate(int64_t m, int64_t n, const int* __restrict__ src,
+                                                     const int* __restrict__ dst,
+                                                     const double* __restrict__ w, int* flags) {
+    int bad_idx = 0, bad_w = 0, noncanon = 0;
+    for (int64_t l = int64_t(blockIdx.x) * kBlock + threadIdx.x; l < m;
+         l += int64_t(gridDim.x) * kBlock) {
+        const int a = src[l], b = dst[l];
+        const double wl = w[l];
+        if (a < 0 || a >= n || b < 0 || b >= n) bad_idx = 1;
+        if (!(wl >= 0.0) || isinf(wl)) bad_w = 1;
+        bool ok = a < b && wl > 0.0;
+        if (ok && l > 0) {
+            const int pa = src[l - 1], pb = dst[l - 1];
+            ok = (pa < a) || (pa == a && pb < b);
+        }
+        if (!ok) noncanon = 1;
+    }
+    if (bad_idx) atomicOr(flags + 0, 1);
+    if (bad_w) atomicOr(flags + 1, 1);
+    if (noncanon) atomicOr(flags + 2, 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_make_keys(int64_t m, const int* __restrict__ src,
+                                                      const int* __restrict__ dst,
+                                                      const double* __restrict__ w,
+                                                      unsigned long long* __restrict__ key) {
+    for (int64_t l = int64_t(blockIdx.x) * kBlock + threadIdx.x; l < m;
+         l += int64_t(gridDim.x) * kBlock) {
+        const unsigned a = unsigned(src[l]), b = unsigned(dst[l]);
+        if (a == b || !(w[l] > 0.0)) {
+            key[l] = ~0ull;
+        } else {
+            const unsigned lo = a < b ? a : b, hi = a < b ? b : a;
+            key[l] = (static_cast<unsigned long long>(lo) << 32) | hi;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_unpack(int64_t m, const unsigned long long* __restrict__ key,
+                                                   int* __restrict__ src, int* __restrict__ dst) {
+    for (int64_t l = int64_t(blockIdx.x) * kBlock + threadIdx.x; l < m;
+         l += int64_t(gridDim.x) * kBlock) {
+        src[l] = int(key[l] >> 32);
+        dst[l] = int(key[l] & 0xffffffffull);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_inc_entries(int64_t m, const int* __restrict__ src,
+                                                        const int* __restrict__ dst,
+                                                        int* __restrict__ vk,
+                                                        Inc* __restrict__ vv) {
+    for (int64_t l = int64_t(blockIdx.x) * kBlock + threadIdx.x; l < m;
+         l += int64_t(gridDim.x) * kBlock) {
+        const int a = src[l], b = dst[l];
+        vk[2 * l] = a;
+        vv[2 * l] = Inc{int(l), b};
+        vk[2 * l + 1] = b;
+        vv[2 * l + 1] = Inc{~int(l), a};
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_inc_ptr(int64_t n, int64_t cnt,
+                                                    const int* __restrict__ vk_sorted,
+                                                    int* __restrict__ ptr, int* max_deg) {
+    int best = 0;
+    for (int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x; v <= n;
+         v += int64_t(gridDim.x) * kBlock) {
+        // first position with key >= v
+        int64_t lo = 0, hi = cnt;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (vk_sorted[mid] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        ptr[v] = int(lo);
+        if (v < n) {
+            int64_t lo2 = lo, hi2 = cnt;
+            while (lo2 < hi2) {
+                const int64_t mid = (lo2 + hi2) >> 1;
+                if (vk_sorted[mid] < v + 1) lo2 = mid + 1;
+                else hi2 = mid;
+            }
+            const int deg = int(lo2 - lo);
+            best = deg > best ? deg : best;
+        }
+    }
+    atomicMax(max_deg, best);
+}
+
+int bits_for(int64_t n) {
+    int b = 1;
+    while ((int64_t(1) << b) <= n) ++b;
+    return b;
+}
+
+#define HIPCHK(expr)                                                      \
+    do {                                                                  \
+        hipError_t e_ = (expr);                                           \
+        if (e_ != hipSuccess) {                                           \
+            err = std::string(#expr) + ": " + hipGetErrorString(e_);      \
+            return e_ == hipErrorOutOfMemory ? CCM_E_NOMEM : CCM_E_HIP;   \
+        }                                                                 \
+    } while (0)
+
+ccm_status canonicalize(const int* src, const int* dst, const double* w, int64_t m, hipStream_t s,
+                        OwnedGraph& out, int64_t& m_c, std::string& err) {
+    DevMem key, key_s, val_s, uniq, agg, nruns, temp;
+    HIPCHK(key.alloc(m * 8, s));
+    HIPCHK(key_s.alloc(m * 8, s));
+    HIPCHK(val_s.alloc(m * 8, s));
+    HIPCHK(uniq.alloc(m * 8, s));
+    HIPCHK(agg.alloc(m * 8, s));
+    HIPCHK(nruns.alloc(8, s));
+    hipLaunchKernelGGL(k_make_keys, dim3(flat_grid(m)), dim3(kBlock), 0, s, m, src, dst, w,
+                       key.as<unsigned long long>());
+    size_t b1 = 0, b2 = 0;
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, b1, key.as<unsigned long long>(),
+                                              key_s.as<unsigned long long>(), w,
+                                              val_s.as<double>(), int(m), 0, 64, s));
+    HIPCHK(hipcub::DeviceReduce::ReduceByKey(nullptr, b2, key_s.as<unsigned long long>(),
+                                             uniq.as<unsigned long long>(), val_s.as<double>(),
+                                             agg.as<double>(), nruns.as<int>(), hipcub::Sum(),
+                                             int(m), s));
+    HIPCHK(temp.alloc(b1 > b2 ? b1 : b2, s));
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(temp.p, b1, key.as<unsigned long long>(),
+                                              key_s.as<unsigned long long>(), w,
+                                              val_s.as<double>(), int(m), 0, 64, s));
+    HIPCHK(hipcub::DeviceReduce::ReduceByKey(temp.p, b2, key_s.as<unsigned long long>(),
+                                             uniq.as<unsigned long long>(), val_s.as<double>(),
+                                             agg.as<double>(), nruns.as<int>(), hipcub::Sum(),
+                                             int(m), s));
+    int runs = 0;
+    HIPCHK(hipMemcpyAsync(&runs, nruns.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    unsigned long long last = 0;
+    if (runs > 0) {
+        HIPCHK(hipMemcpyAsync(&last, uniq.as<unsigned long long>() + runs - 1, 8,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    m_c = runs - ((runs > 0 && last == ~0ull) ? 1 : 0);
+    HIPCHK(out.src.alloc(m_c * 4, s));
+    HIPCHK(out.dst.alloc(m_c * 4, s));
+    HIPCHK(out.w.alloc(m_c * 8, s));
+    if (m_c > 0) {
+        hipLaunchKernelGGL(k_unpack, dim3(flat_grid(m_c)), dim3(kBlock), 0, s, m_c,
+                           uniq.as<unsigned long long>(), out.src.as<int>(), out.dst.as<int>());
+        HIPCHK(hipMemcpyAsync(out.w.p, agg.p, m_c * 8, hipMemcpyDeviceToDevice, s));
+    }
+    return CCM_OK;
+}
+
+ccm_status validate(const int* src, const int* dst, const double* w, int64_t m, int64_t n,
+                    hipStream_t s, bool& canonical, std::string& err) {
+    canonical = true;
+    if (m == 0) return CCM_OK;
+    DevMem flags;
+    HIPCHK(flags.alloc(3 * sizeof(int), s));
+    HIPCHK(hipMemsetAsync(flags.p, 0, 3 * sizeof(int), s));
+    hipLaunchKernelGGL(k_validate, dim3(flat_grid(m)), dim3(kBlock), 0, s, m, n, src, dst, w,
+                       flags.as<int>());
+    int h[3] = {0, 0, 0};
+    HIPCHK(hipMemcpyAsync(h, flags.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h[0]) {
+        err = "edge endpoint outside [0, n)";
+        return CCM_E_INVALID;
+    }
+    if (h[1]) {
+        err = "edge weight negative or not finite";
+        return CCM_E_INVALID;
+    }
+    canonical = h[2] == 0;
+    return CCM_OK;
+}
+
+}  // namespace
+
+ccm_status graph_canonical_count(const int* src, const int* dst, const double* w, int64_t m,
+                                 int64_t n, hipStream_t s, int64_t& m_canon, std::string& err) {
+    bool canonical = true;
+    ccm_status st = validate(src, dst, w, m, n, s, canonical, err);
+    if (st != CCM_OK) return st;
+    if (canonical) {
+        m_canon = m;
+        return CCM_OK;
+    }
+    OwnedGraph tmp;
+    return canonicalize(src, dst, w, m, s, tmp, m_canon, err);
+}
+
+ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t m, int64_t n,
+                       bool require_canonical, hipStream_t s, OwnedGraph& out, std::string& err) {
+    if (n < 1 || n > (int64_t(1) << 30) || m < 0 || m > (int64_t(1) << 30)) {
+        err = "graph size out of range";
+        return CCM_E_INVALID;
+    }
+    bool canonical = true;
+    ccm_status st = validate(src, dst, w, m, n, s, canonical, err);
+    if (st != CCM_OK) return st;
+    int64_t mc = m;
+    if (!canonical) {
+        if (require_canonical) {
+            err = "edges must be canonical (src < dst, sorted by (src, dst), w > 0)";
+            return CCM_E_INVALID;
+        }
+        st = canonicalize(src, dst, w, m, s, out, mc, err);
+        if (st != CCM_OK) return st;
+        out.g.src = out.src.as<int>();
+        out.g.dst = out.dst.as<int>();
+        out.g.w = out.w.as<double>();
+    } else {
+        out.g.src = src;
+        out.g.dst = dst;
+        out.g.w = w;
+    }
+    out.g.n = n;
+    out.g.m = mc;
+    // vertex-major incidence lists: entries (vertex, edge) sorted stably by
+    // vertex keep each list in ascending edge order
+    const int64_t cnt = 2 * mc;
+    DevMem vk, vk_s, vv, temp, maxdeg;
+    HIPCHK(vk.alloc(cnt * 4, s));
+    HIPCHK(vk_s.alloc(cnt * 4, s));
+    HIPCHK(vv.alloc(cnt * 8, s));
+    HIPCHK(out.inc.alloc(cnt * 8, s));
+    HIPCHK(out.inc_ptr.alloc((n + 1) * 4, s));
+    HIPCHK(maxdeg.alloc(4, s));
+    HIPCHK(hipMemsetAsync(maxdeg.p, 0, 4, s));
+    if (mc > 0) {
+        hipLaunchKernelGGL(k_inc_entries, dim3(flat_grid(mc)), dim3(kBlock), 0, s, mc, out.g.src,
+                           out.g.dst, vk.as<int>(), vv.as<Inc>());
+        size_t b = 0;
+        const int nb = bits_for(n);
+        HIPCHK(hipcub::DeviceRadixSort::SortPairs(
+            nullptr, b, vk.as<int>(), vk_s.as<int>(), vv.as<unsigned long long>(),
+            out.inc.as<unsigned long long>(), int(cnt), 0, nb, s));
+        HIPCHK(temp.alloc(b, s));
+        HIPCHK(hipcub::DeviceRadixSort::SortPairs(
+            temp.p, b, vk.as<int>(), vk_s.as<int>(), vv.as<unsigned long long>(),
+            out.inc.as<unsigned long long>(), int(cnt), 0, nb, s));
+    }
+    hipLaunchKernelGGL(k_inc_ptr, dim3(flat_grid(n + 1)), dim3(kBlock), 0, s, n, cnt,
+                       vk_s.as<int>(), out.inc_ptr.as<int>(), maxdeg.as<int>());
+    int md = 0;
+    HIPCHK(hipMemcpyAsync(&md, maxdeg.p, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    out.g.inc_ptr = out.inc_ptr.as<int>();
+    out.g.inc = out.inc.as<Inc>();
+    out.g.max_deg = md;
+    return CCM_OK;
+}
+
+}  // namespace ccm

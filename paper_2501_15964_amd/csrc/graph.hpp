@@ -1,0 +1,49 @@
+// Device graph construction: validation, canonical edge list and the
+// vertex-major incidence lists (CSR by vertex).
+#pragma once
+#include <string>
+
+#include "../../include/ccm.h"
+#include "launch.hpp"
+
+namespace ccm {
+
+// Stream-ordered device allocation that is released when the object dies.
+struct DevMem {
+    void* p = nullptr;
+    hipStream_t s = nullptr;
+    DevMem() = default;
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    ~DevMem() { release(); }
+    void release() {
+        if (p) (void)hipFreeAsync(p, s);
+        p = nullptr;
+    }
+    hipError_t alloc(size_t bytes, hipStream_t st) {
+        release();
+        s = st;
+        if (bytes == 0) bytes = 8;
+        return hipMallocAsync(&p, bytes, st);
+    }
+    template <class T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+struct OwnedGraph {
+    DevGraph g;
+    DevMem src, dst, w, inc_ptr, inc;
+};
+
+// Builds `out` from caller edges.  With require_canonical the edges must
+// already be canonical (src < dst, strictly increasing (src, dst), w > 0)
+// and are referenced in place; otherwise they are canonicalised into owned
+// arrays.  Returns CCM_OK or an error with text in `err`.  Synchronises s.
+ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t m, int64_t n,
+                       bool require_canonical, hipStream_t s, OwnedGraph& out, std::string& err);
+
+// Number of canonical edges for the given input (synchronises s).
+ccm_status graph_canonical_count(const int* src, const int* dst, const double* w, int64_t m,
+                                 int64_t n, hipStream_t s, int64_t& m_canon, std::string& err);
+
+}  // namespace ccm

@@ -1,0 +1,330 @@
+// Exact k-NN search and the union-symmetrised Gaussian weight graph.
+//
+// Squared distances are accumulated feature by feature in ascending order
+// with separately rounded products and sums (no fused multiply-add), so every
+// d^2 is bit-defined and the neighbour order (d^2, index) is reproducible.
+// A block owns 128 query rows (one per thread, held transposed in LDS) and
+// streams tiles of 32 candidate rows through LDS; each thread keeps its best
+// KP candidates in registers with a fixed-shape insertion network.  Candidate
+// columns are split over blockIdx.y; a second pass merges the partial lists.
+#include <hipcub/hipcub.hpp>
+
+#include "knn.hpp"
+
+namespace ccm {
+namespace {
+
+constexpr int kQT = 128;  // query rows per block
+constexpr int kCT = 32;   // candidate rows per tile
+constexpr int kDK = 64;   // features per LDS chunk
+
+__device__ __forceinline__ bool knn_less(double da, int ja, double db, int jb) {
+    return da < db || (da == db && ja < jb);
+}
+
+template <int KP>
+__device__ __forceinline__ void knn_insert(double (&bd)[KP], int (&bi)[KP], double dv, int j) {
+    if (!knn_less(dv, j, bd[KP - 1], bi[KP - 1])) return;
+    bool placed = false;
+#pragma unroll
+    for (int p = KP - 1; p >= 1; --p) {
+        if (!placed) {
+            if (knn_less(dv, j, bd[p - 1], bi[p - 1])) {
+                bd[p] = bd[p - 1];
+                bi[p] = bi[p - 1];
+            } else {
+                bd[p] = dv;
+                bi[p] = j;
+                placed = true;
+            }
+        }
+    }
+    if (!placed) {
+        bd[0] = dv;
+        bi[0] = j;
+    }
+}
+
+template <int KP>
+__global__ __launch_bounds__(kQT) void k_knn_partial(const double* __restrict__ A, int64_t n, int d,
+                                                     int64_t cols_per_split,
+                                                     double* __restrict__ pd,
+                                                     int* __restrict__ pi) {
+    __shared__ double Qs[kDK][kQT];
+    __shared__ double Cs[kCT][kDK + 1];
+    const int tid = threadIdx.x;
+    const int64_t q0 = int64_t(blockIdx.x) * kQT;
+    const int64_t qi = q0 + tid;
+    const int64_t c_begin = int64_t(blockIdx.y) * cols_per_split;
+    int64_t c_end = c_begin + cols_per_split;
+    if (c_end > n) c_end = n;
+    double bd[KP];
+    int bi[KP];
+#pragma unroll
+    for (int p = 0; p < KP; ++p) {
+        bd[p] = INFINITY;
+        bi[p] = 0x7fffffff;
+    }
+    for (int64_t c0 = c_begin; c0 < c_end; c0 += kCT) {
+        double acc[kCT];
+#pragma unroll
+        for (int c = 0; c < kCT; ++c) acc[c] = 0.0;
+        for (int k0 = 0; k0 < d; k0 += kDK) {
+            const int dk = (d - k0) < kDK ? (d - k0) : kDK;
+            __syncthreads();
+            for (int e = tid; e < kQT * kDK; e += kQT) {
+                const int t = e / kDK, k = e % kDK;
+                const int64_t row = q0 + t;
+                Qs[k][t] = (row < n && k < dk) ? A[row * d + k0 + k] : 0.0;
+            }
+            for (int e = tid; e < kCT * kDK; e += kQT) {
+                const int c = e / kDK, k = e % kDK;
+                const int64_t row = c0 + c;
+                Cs[c][k] = (row < c_end && k < dk) ? A[row * d + k0 + k] : 0.0;
+            }
+            __syncthreads();
+            {
+                // separately rounded subtract, multiply and add: no contraction
+                // into fused multiply-adds, so each d^2 is bit-defined
+#pragma clang fp contract(off)
+                for (int k = 0; k < dk; ++k) {
+                    const double qv = Qs[k][tid];
+#pragma unroll
+                    for (int c = 0; c < kCT; ++c) {
+                        const double df = qv - Cs[c][k];
+                        const double sq = df * df;
+                        acc[c] = acc[c] + sq;
+                    }
+                }
+            }
+        }
+        if (qi < n) {
+#pragma unroll
+            for (int c = 0; c < kCT; ++c) {
+                const int64_t j = c0 + c;
+                if (j < c_end && j != qi) knn_insert<KP>(bd, bi, acc[c], int(j));
+            }
+        }
+    }
+    if (qi < n) {
+        const int64_t base = (int64_t(blockIdx.y) * n + qi) * KP;
+#pragma unroll
+        for (int p = 0; p < KP; ++p) {
+            pd[base + p] = bd[p];
+            pi[base + p] = bi[p];
+        }
+    }
+}
+
+template <int KP>
+__global__ __launch_bounds__(kBlock) void k_knn_merge(int64_t n, int k, int splits,
+                                                      const double* __restrict__ pd,
+                                                      const int* __restrict__ pi,
+                                                      int* __restrict__ nbr,
+                                                      double* __restrict__ nd2) {
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * kBlock) {
+        double bd[KP];
+        int bi[KP];
+#pragma unroll
+        for (int p = 0; p < KP; ++p) {
+            bd[p] = INFINITY;
+            bi[p] = 0x7fffffff;
+        }
+        for (int sp = 0; sp < splits; ++sp) {
+            const int64_t base = (int64_t(sp) * n + i) * KP;
+            for (int p = 0; p < KP; ++p) {
+                const int j = pi[base + p];
+                if (j == 0x7fffffff) break;
+                knn_insert<KP>(bd, bi, pd[base + p], j);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < KP; ++p) {
+            if (p < k) {
+                nbr[i * k + p] = bi[p];
+                nd2[i * k + p] = bd[p];
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pair_keys(int64_t n, int k, const int* __restrict__ nbr,
+                                                      unsigned long long* __restrict__ key) {
+    const int64_t cnt = n * k;
+    for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < cnt;
+         e += int64_t(gridDim.x) * kBlock) {
+        const unsigned i = unsigned(e / k), j = unsigned(nbr[e]);
+        const unsigned lo = i < j ? i : j, hi = i < j ? j : i;
+        key[e] = (static_cast<unsigned long long>(lo) << 32) | hi;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_weights(int64_t m, const unsigned long long* __restrict__ key,
+                                                    const double* __restrict__ d2, double phi,
+                                                    int* __restrict__ keep,
+                                                    double* __restrict__ wtmp) {
+    for (int64_t l = int64_t(blockIdx.x) * kBlock + threadIdx.x; l < m;
+         l += int64_t(gridDim.x) * kBlock) {
+        const double wv = exp(-phi * d2[l]);
+        wtmp[l] = wv;
+        keep[l] = wv > 0.0 ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_emit(int64_t m, const unsigned long long* __restrict__ key,
+                                                 const double* __restrict__ wtmp,
+                                                 const int* __restrict__ keep,
+                                                 const int* __restrict__ pos,
+                                                 int* __restrict__ src, int* __restrict__ dst,
+                                                 double* __restrict__ w) {
+    for (int64_t l = int64_t(blockIdx.x) * kBlock + threadIdx.x; l < m;
+         l += int64_t(gridDim.x) * kBlock) {
+        if (!keep[l]) continue;
+        const int p = pos[l];
+        src[p] = int(key[l] >> 32);
+        dst[p] = int(key[l] & 0xffffffffull);
+        w[p] = wtmp[l];
+    }
+}
+
+__global__ void k_median(const double* __restrict__ sorted, int64_t cnt, double* out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (cnt % 2 == 1) out[0] = sorted[cnt / 2];
+        else out[0] = (sorted[cnt / 2 - 1] + sorted[cnt / 2]) / 2.0;
+    }
+}
+
+#define HIPCHK(expr)                                                      \
+    do {                                                                  \
+        hipError_t e_ = (expr);                                           \
+        if (e_ != hipSuccess) {                                           \
+            err = std::string(#expr) + ": " + hipGetErrorString(e_);      \
+            return e_ == hipErrorOutOfMemory ? CCM_E_NOMEM : CCM_E_HIP;   \
+        }                                                                 \
+    } while (0)
+
+template <int KP>
+void launch_knn(const double* A, int64_t n, int d, int k, int splits, int64_t cps, double* pd,
+                int* pi, int* nbr, double* nd2, hipStream_t s) {
+    dim3 grid(unsigned((n + kQT - 1) / kQT), unsigned(splits));
+    hipLaunchKernelGGL((k_knn_partial<KP>), grid, dim3(kQT), 0, s, A, n, d, cps, pd, pi);
+    hipLaunchKernelGGL((k_knn_merge<KP>), dim3(flat_grid(n)), dim3(kBlock), 0, s, n, k, splits,
+                       pd, pi, nbr, nd2);
+}
+
+}  // namespace
+
+ccm_status knn_graph(const double* A, int64_t n, int d, int k, double phi, int* src, int* dst,
+                     double* w, int64_t m_cap, int64_t& m_out, double& phi_out, hipStream_t s,
+                     std::string& err) {
+    const int KP = k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : 32;
+    // split candidate columns so that the grid has enough blocks
+    const int64_t qblocks = (n + kQT - 1) / kQT;
+    int64_t splits = (2048 + qblocks - 1) / qblocks;
+    const int64_t ctiles = (n + kCT - 1) / kCT;
+    if (splits > ctiles) splits = ctiles;
+    if (splits < 1) splits = 1;
+    int64_t cps = ((ctiles + splits - 1) / splits) * kCT;
+    splits = (n + cps - 1) / cps;
+    const int64_t cnt = n * k;
+    DevMem pd, pi, nbr, nd2;
+    HIPCHK(pd.alloc(size_t(splits) * n * KP * 8, s));
+    HIPCHK(pi.alloc(size_t(splits) * n * KP * 4, s));
+    HIPCHK(nbr.alloc(size_t(cnt) * 4, s));
+    HIPCHK(nd2.alloc(size_t(cnt) * 8, s));
+    switch (KP) {
+        case 4: launch_knn<4>(A, n, d, k, int(splits), cps, pd.as<double>(), pi.as<int>(),
+                              nbr.as<int>(), nd2.as<double>(), s); break;
+        case 8: launch_knn<8>(A, n, d, k, int(splits), cps, pd.as<double>(), pi.as<int>(),
+                              nbr.as<int>(), nd2.as<double>(), s); break;
+        case 16: launch_knn<16>(A, n, d, k, int(splits), cps, pd.as<double>(), pi.as<int>(),
+                                nbr.as<int>(), nd2.as<double>(), s); break;
+        default: launch_knn<32>(A, n, d, k, int(splits), cps, pd.as<double>(), pi.as<int>(),
+                                nbr.as<int>(), nd2.as<double>(), s); break;
+    }
+    HIPCHK(hipGetLastError());
+    pd.release();
+    pi.release();
+    // phi = 1 / median of the n k directed distances when not given
+    if (!(phi > 0)) {
+        DevMem sorted, temp, med;
+        HIPCHK(sorted.alloc(size_t(cnt) * 8, s));
+        HIPCHK(med.alloc(8, s));
+        size_t tb = 0;
+        HIPCHK(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, nd2.as<double>(),
+                                                 sorted.as<double>(), int(cnt), 0, 64, s));
+        HIPCHK(temp.alloc(tb, s));
+        HIPCHK(hipcub::DeviceRadixSort::SortKeys(temp.p, tb, nd2.as<double>(),
+                                                 sorted.as<double>(), int(cnt), 0, 64, s));
+        hipLaunchKernelGGL(k_median, dim3(1), dim3(64), 0, s, sorted.as<double>(), cnt,
+                           med.as<double>());
+        double h = 0;
+        HIPCHK(hipMemcpyAsync(&h, med.p, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        phi = h > 0 ? 1.0 / h : 1.0;
+    }
+    phi_out = phi;
+    // union symmetrisation: one key per unordered pair; both directions carry
+    // the same d^2 bit for bit, so keeping the minimum keeps that value
+    DevMem key, key_s, d2_s, uniq, d2u, nruns, temp2;
+    HIPCHK(key.alloc(size_t(cnt) * 8, s));
+    HIPCHK(key_s.alloc(size_t(cnt) * 8, s));
+    HIPCHK(d2_s.alloc(size_t(cnt) * 8, s));
+    HIPCHK(uniq.alloc(size_t(cnt) * 8, s));
+    HIPCHK(d2u.alloc(size_t(cnt) * 8, s));
+    HIPCHK(nruns.alloc(8, s));
+    hipLaunchKernelGGL(k_pair_keys, dim3(flat_grid(cnt)), dim3(kBlock), 0, s, n, k, nbr.as<int>(),
+                       key.as<unsigned long long>());
+    size_t b1 = 0, b2 = 0;
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, b1, key.as<unsigned long long>(),
+                                              key_s.as<unsigned long long>(), nd2.as<double>(),
+                                              d2_s.as<double>(), int(cnt), 0, 64, s));
+    HIPCHK(hipcub::DeviceReduce::ReduceByKey(nullptr, b2, key_s.as<unsigned long long>(),
+                                             uniq.as<unsigned long long>(), d2_s.as<double>(),
+                                             d2u.as<double>(), nruns.as<int>(), hipcub::Min(),
+                                             int(cnt), s));
+    HIPCHK(temp2.alloc(b1 > b2 ? b1 : b2, s));
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(temp2.p, b1, key.as<unsigned long long>(),
+                                              key_s.as<unsigned long long>(), nd2.as<double>(),
+                                              d2_s.as<double>(), int(cnt), 0, 64, s));
+    HIPCHK(hipcub::DeviceReduce::ReduceByKey(temp2.p, b2, key_s.as<unsigned long long>(),
+                                             uniq.as<unsigned long long>(), d2_s.as<double>(),
+                                             d2u.as<double>(), nruns.as<int>(), hipcub::Min(),
+                                             int(cnt), s));
+    int runs = 0;
+    HIPCHK(hipMemcpyAsync(&runs, nruns.p, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    // weights, dropping underflowed ones
+    DevMem keep, pos, wtmp, temp3, total;
+    HIPCHK(keep.alloc(size_t(runs + 1) * 4, s));
+    HIPCHK(pos.alloc(size_t(runs + 1) * 4, s));
+    HIPCHK(wtmp.alloc(size_t(runs + 1) * 8, s));
+    hipLaunchKernelGGL(k_weights, dim3(flat_grid(runs)), dim3(kBlock), 0, s, int64_t(runs),
+                       uniq.as<unsigned long long>(), d2u.as<double>(), phi, keep.as<int>(),
+                       wtmp.as<double>());
+    size_t b3 = 0;
+    HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, b3, keep.as<int>(), pos.as<int>(), runs, s));
+    HIPCHK(temp3.alloc(b3, s));
+    HIPCHK(hipcub::DeviceScan::ExclusiveSum(temp3.p, b3, keep.as<int>(), pos.as<int>(), runs, s));
+    int hp[2] = {0, 0};
+    if (runs > 0) {
+        HIPCHK(hipMemcpyAsync(&hp[0], pos.as<int>() + runs - 1, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hp[1], keep.as<int>() + runs - 1, 4, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    m_out = runs > 0 ? int64_t(hp[0]) + hp[1] : 0;
+    if (m_out > m_cap) {
+        err = "m_cap too small for the k-NN graph";
+        return CCM_E_CAPACITY;
+    }
+    if (runs > 0)
+        hipLaunchKernelGGL(k_emit, dim3(flat_grid(runs)), dim3(kBlock), 0, s, int64_t(runs),
+                           uniq.as<unsigned long long>(), wtmp.as<double>(), keep.as<int>(),
+                           pos.as<int>(), src, dst, w);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return CCM_OK;
+}
+
+}  // namespace ccm

@@ -1,0 +1,203 @@
+// Host-side launch interface between the solver drivers and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "common.hpp"
+
+namespace ccm {
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// Row layout: LPR lanes of a wave handle one row of d values, NPER values
+// per lane (coordinate k = lane_in_group + LPR * t).  Rows of up to 64
+// values use one value per lane; longer rows use the whole wave.
+inline bool row_supported(int64_t d) { return d >= 1 && d <= 1024; }
+
+template <class F>
+inline void dispatch_row(int d, F&& f) {
+    if (d <= 1) f(IC<1>{}, IC<1>{});
+    else if (d <= 2) f(IC<2>{}, IC<1>{});
+    else if (d <= 4) f(IC<4>{}, IC<1>{});
+    else if (d <= 8) f(IC<8>{}, IC<1>{});
+    else if (d <= 16) f(IC<16>{}, IC<1>{});
+    else if (d <= 32) f(IC<32>{}, IC<1>{});
+    else if (d <= 64) f(IC<64>{}, IC<1>{});
+    else if (d <= 128) f(IC<64>{}, IC<2>{});
+    else if (d <= 256) f(IC<64>{}, IC<4>{});
+    else if (d <= 512) f(IC<64>{}, IC<8>{});
+    else f(IC<64>{}, IC<16>{});
+}
+
+template <class F>
+inline void dispatch_q(int qk, F&& f) {
+    if (qk == kQ1) f(IC<kQ1>{});
+    else if (qk == kQ2) f(IC<kQ2>{});
+    else f(IC<kQInf>{});
+}
+
+inline int lanes_per_row(int d) {
+    int l = 1;
+    dispatch_row(d, [&](auto L, auto) { l = decltype(L)::value; });
+    return l;
+}
+
+// grid for a grid-stride loop over `rows` rows of LPR lanes
+inline int row_grid(int64_t rows, int lpr) {
+    const int64_t gpb = kBlock / lpr;
+    int64_t g = (rows + gpb - 1) / gpb;
+    if (g < 1) g = 1;
+    if (g > kMaxGrid) g = kMaxGrid;
+    return int(g);
+}
+
+inline int flat_grid(int64_t count) {
+    int64_t g = (count + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > kMaxGrid) g = kMaxGrid;
+    return int(g);
+}
+
+// 64-bit payload words per edge for the bit masks of the q = 1 / q = inf
+// generalized Jacobians (one word per row slice t).
+inline int mask_words(int d) {
+    const int lpr = lanes_per_row(d);
+    return (d + lpr - 1) / lpr;
+}
+
+// Per-edge generalized-Jacobian payload written by the SSNAL edge pass.
+struct Payload {
+    double* alpha = nullptr;   // q = 2: r/||y|| outside the ball, 1 inside
+    uint64_t* bits = nullptr;  // q = 1: in-box mask; q = inf: support and sign masks
+    int* cnt = nullptr;        // q = inf: -1 inside the ball, else support size
+};
+
+struct DevGraph {
+    int64_t n = 0, m = 0;
+    const int* src = nullptr;
+    const int* dst = nullptr;
+    const double* w = nullptr;
+    const int* inc_ptr = nullptr;  // n + 1
+    const Inc* inc = nullptr;      // 2 m
+    int max_deg = 0;
+};
+
+// ---- edge kernels (edge_kernels.hip) --------------------------------------
+// SSNAL edge pass: Y = U + sigma B X, Pi = Pi_C(Y), payload; partials per
+// block (5): <BX, Pi>, ||Pi - U||^2, ||BX||^2, ||Pi||^2, and the number of
+// edges whose Jacobian is not the identity (outside the ball).
+constexpr int kEdgeSsnalNV = 5;
+int launch_edge_ssnal(const DevGraph& g, int d, int qk, double gamma, double sigma,
+                      const double* X, const double* U, double* Pi, Payload pl,
+                      double* partials, hipStream_t s);
+
+// KKT edge pass for (X, U): partials (6): ||Pi_C(BX+U) - U||^2, ||BX||^2,
+// ||U||^2, ||U - Pi_C(U)||^2, sum_l r_l ||(BX)_l||_q, 0.  Optionally writes
+// Pi_C(U) to Ufeas.
+constexpr int kEdgeKktNV = 6;
+int launch_edge_kkt(const DevGraph& g, int d, int qk, double gamma, const double* X,
+                    const double* U, double* Ufeas, double* partials, hipStream_t s);
+
+// ADMM edge step: Pi = Pi_C(sigma BX + L), Z <- BX + (L - Pi)/sigma,
+// L <- L + tau sigma (BX - Z), Q <- sigma Z - L, optional Uf <- Pi_C(L).
+// partials (4): ||BX - Z||^2, ||Z - Zold||^2, ||BX||^2, ||Z||^2.
+constexpr int kEdgeAdmmNV = 4;
+int launch_edge_admm(const DevGraph& g, int d, int qk, double gamma, double sigma, double tau,
+                     const double* X, double* Z, double* L, double* Q, double* Uf,
+                     double* partials, hipStream_t s);
+
+// Fast AMA edge step on the dual: Unew = Pi_C(V + nu B X); then with momentum
+// coefficient beta: Vnew = Unew + beta (Unew - U); U <- Unew.  partials (2):
+// <V - Unew, Unew - U> (restart test), ||Unew - U||^2.
+constexpr int kEdgeAmaNV = 2;
+int launch_edge_ama(const DevGraph& g, int d, int qk, double gamma, double nu, double beta,
+                    const double* X, double* U, double* V, double* partials, hipStream_t s);
+
+void launch_gather(const DevGraph& g, int d, const double* X, double* Y, hipStream_t s);
+void launch_project(int64_t m, int d, int qk, const double* Y, const double* w, double gamma,
+                    bool prox, double* out, hipStream_t s);
+// fused[l] = ||x_src - x_dst||_2 <= thr
+void launch_fused_flags(const DevGraph& g, int d, const double* X, double thr, int* fused,
+                        hipStream_t s);
+
+// ---- vertex kernels (vertex_kernels.hip) ----------------------------------
+// out = cx X + ca A + cz B^T Z (X or A may be null).  With `diag` (SSNAL),
+// also Dinv = 1 / (1 + sigma diag(B^T P B)) from the payload.  partials (4):
+// ||out||^2, 1/2 ||X - A||^2, <A, B^T Z>, ||B^T Z||^2.
+constexpr int kScatterNV = 4;
+int launch_scatter(const DevGraph& g, int d, int qk, double cx, const double* X, double ca,
+                   const double* A, double cz, const double* Z, double* out, bool diag,
+                   Payload pl, double gamma, double sigma, double* Dinv, double* partials,
+                   hipStream_t s);
+
+// Newton matvec: out = c0 V + sigma sum_{l ~ i} P_l (v_i - v_other) with the
+// SSNAL payload (mode 0) or P_l = I (mode 1, the ADMM matrix I + sigma B^T B).
+// Optional per-vertex diagonal scale `dscale` (n values) replaces c0.
+// partials (1): <V, out>.  If rr_partials is non-null the kernel returns at
+// once when the CG residual recorded there is below thr or *done is set.
+struct CgSkip {
+    const double* rr_partials = nullptr;
+    int nparts = 0;
+    double thr = 0.0;
+    const int* done = nullptr;
+};
+constexpr int kMatvecNV = 1;
+int launch_matvec(const DevGraph& g, int d, int qk, int mode, const double* V, const double* Pi,
+                  Payload pl, double gamma, double sigma, double c0, const double* dscale,
+                  double* out, double* partials, CgSkip skip, hipStream_t s);
+
+// ---- vector kernels (vector_kernels.hip) ----------------------------------
+struct CgBufs {
+    double *x, *r, *u, *w, *p, *s;  // n*d each
+    double* upd[2];                 // update partials (r.u, r.r) per block, parity buffered
+    double* wu[2];                  // matvec partials (w.u) per block, parity buffered
+    double* state;                  // [2][2]: gamma_j, alpha_j per parity
+    int* flag;                      // [0] done (1) / breakdown (2), [1] iterations
+    int nparts;                     // partial count of the update kernel
+    int nparts_mv;                  // partial count of the matvec kernel
+};
+// r = b (or -b when neg), u = Dinv r, x = p = s = 0; partials ru[0], rr[0].
+void launch_cg_init(int64_t N, const double* b, bool neg, const double* Dinv, CgBufs& cg,
+                    hipStream_t s);
+// iteration j of the Chronopoulos-Gear PCG update (see vector_kernels.hip).
+void launch_cg_update(int64_t N, int j, const double* Dinv, CgBufs& cg, double thr, hipStream_t s);
+int cg_update_grid(int64_t N);
+
+// Xt = X + alpha D; partials (2): 1/2 ||Xt - A||^2, <G, D>.
+constexpr int kAxpyNV = 2;
+int launch_trial(int64_t N, const double* X, const double* D, double alpha, const double* A,
+                 const double* G, double* Xt, double* partials, hipStream_t s);
+// sum partials[p * nv + c] over p for every c; out[c] = total.
+void launch_finalize(const double* partials, int nparts, int nv, double* out, hipStream_t s);
+void launch_fill(double* x, int64_t N, double v, hipStream_t s);
+// x += alpha y
+void launch_axpy(double* x, double alpha, const double* y, int64_t N, hipStream_t s);
+// out = a x + b y
+void launch_axpby(double a, const double* x, double b, const double* y, double* out, int64_t N,
+                  hipStream_t s);
+// partials (1): <x, y>
+int launch_dot(const double* x, const double* y, int64_t N, double* partials, hipStream_t s);
+void launch_copy(const double* a, double* b, int64_t N, hipStream_t s);
+// out = a - b (elementwise)
+void launch_sub(const double* a, const double* b, double* out, int64_t N, hipStream_t s);
+// Dinv[i, :] = 1 / (c0 + sigma deg_i)
+void launch_lap_dinv(const DevGraph& g, int d, double c0, double sigma, double* Dinv,
+                     hipStream_t s);
+// column sums partials of A (n x d): partials[p * d + k]; then spread
+// S = max_i ||a_i - mean||; result written to out[0].
+void launch_spread(const double* A, int64_t n, int d, double* work, double* out, hipStream_t s);
+int spread_work_size(int64_t n, int d);
+void launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
+
+// ---- labels (labels.hip) --------------------------------------------------
+// labels from fused flags: connected components, numbered by smallest vertex.
+// work: int[n] parent + int[n + 1] scan + hipcub temp.  n_clusters (device int).
+size_t labels_temp_bytes(int64_t n);
+void launch_labels(int64_t n, int64_t m, const int* src, const int* dst, const int* fused,
+                   int* parent, int* rank, void* temp, size_t temp_bytes, int* labels,
+                   int* n_clusters, hipStream_t s);
+
+}  // namespace ccm

@@ -1,0 +1,757 @@
+// Host drivers of the path solvers: SSNAL (semismooth Newton augmented
+// Lagrangian), ADMM and fast AMA for the convex clustering model, warm-started
+// along a gamma sequence.  Every arithmetic step runs in the HIP kernels; the
+// host only sequences launches and reads back a handful of FP64 scalars
+// (objective pieces, residual norms, CG status) to take control decisions.
+#include "solver.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace ccm {
+
+namespace {
+
+#define HIPCHK(expr)                                                      \
+    do {                                                                  \
+        hipError_t e_ = (expr);                                           \
+        if (e_ != hipSuccess) {                                           \
+            err = std::string(#expr) + ": " + hipGetErrorString(e_);      \
+            return e_ == hipErrorOutOfMemory ? CCM_E_NOMEM : CCM_E_HIP;   \
+        }                                                                 \
+    } while (0)
+
+#define CHK(expr)                              \
+    do {                                       \
+        ccm_status st_ = (expr);               \
+        if (st_ != CCM_OK) return st_;         \
+    } while (0)
+
+using Clock = std::chrono::steady_clock;
+
+// scalar slots in the device/host scalar block
+enum Slot {
+    kE = 0,    // edge pass at the current point (5)
+    kS = 5,    // scatter at the current point (4)
+    kT = 9,    // trial axpy (2)
+    kET = 11,  // edge pass at the trial point (5)
+    kST = 16,  // scatter at the trial point (4)
+    kK = 20,   // KKT edge pass (6)
+    kM = 26,   // misc (ADMM residuals, dots) (8)
+    kNA = 34,  // ||A||^2
+    kSP = 35,  // data spread S
+    kNS = 40
+};
+
+// HIP-event timing of kernel classes (ccm_options.profile)
+struct Prof {
+    bool on = false;
+    hipStream_t s = nullptr;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> cls;
+    size_t used = 0;
+    double ms[CCM_NK] = {0};
+    int64_t calls[CCM_NK] = {0};
+    int open_cls = -1;
+    ~Prof() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    void begin(int c) {
+        if (!on) return;
+        if (used + 2 > ev.size()) {
+            for (int k = 0; k < 64; ++k) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) == hipSuccess) ev.push_back(e);
+            }
+            cls.resize(ev.size() / 2 + 1);
+        }
+        if (used + 2 > ev.size()) return;
+        (void)hipEventRecord(ev[used], s);
+        open_cls = c;
+    }
+    void end() {
+        if (!on || open_cls < 0) return;
+        (void)hipEventRecord(ev[used + 1], s);
+        cls[used / 2] = open_cls;
+        used += 2;
+        open_cls = -1;
+    }
+    // after a stream synchronisation: accumulate every recorded pair
+    void harvest() {
+        if (!on) return;
+        for (size_t k = 0; k + 1 < used; k += 2) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) == hipSuccess) {
+                ms[cls[k / 2]] += t;
+                calls[cls[k / 2]] += 1;
+            }
+        }
+        used = 0;
+    }
+    void take(ccm_stats& st) {
+        for (int c = 0; c < CCM_NK; ++c) {
+            st.kern_ms[c] = ms[c];
+            st.kern_calls[c] = calls[c];
+            ms[c] = 0;
+            calls[c] = 0;
+        }
+    }
+};
+
+struct Timed {
+    Prof& p;
+    Timed(Prof& pr, int c) : p(pr) { p.begin(c); }
+    ~Timed() { p.end(); }
+};
+
+struct Ev {
+    double phi = 0, gn = 0, rp = 0;
+    double G2 = 0, hx = 0, aBtPi = 0, BtPi2 = 0;
+    double bxpi = 0, pu2 = 0, bx2 = 0, pi2 = 0, nout = 0;
+};
+
+}  // namespace
+
+struct Solver::Impl {
+    // problem
+    const DevGraph& g;
+    int d;
+    int64_t n, m, N, M;
+    int qk;
+    const double* A;
+    hipStream_t s;
+    ccm_options o;
+    double tol;
+    std::string& err;
+    Prof prof;
+    Clock::time_point t_start;
+
+    // vertex buffers
+    DevMem bX, bXt, bG, bGt, bDinv, bDinvt, bTmp, bTmp2;
+    DevMem cgx, cgr, cgu, cgw, cgp, cgs;
+    // edge buffers
+    DevMem bU, bPi, bPit, bZ, bL, bQ, bZold;
+    DevMem al0, al1, bi0, bi1, cn0, cn1;
+    DevMem fused, parent, rank, ltemp;
+    size_t ltemp_bytes = 0;
+    // reductions
+    DevMem pe, pet, ps, pst, pt, pk, pm, pm2, pupd0, pupd1, pwu0, pwu1, dsc, cgstate, cgflag,
+        spread_work;
+    double* hs = nullptr;
+    int* hflag = nullptr;
+    CgBufs cg{};
+
+    double *X = nullptr, *Xt = nullptr, *G = nullptr, *Gt = nullptr, *Dinv = nullptr,
+           *Dinvt = nullptr, *U = nullptr, *Pi = nullptr, *Pit = nullptr;
+    Payload pl{}, plt{};
+    double nA = 0, spread = 0;
+    bool have_U = false;  // U holds a multiplier (else zero)
+    double sigma = 0;
+    // ADMM state validity
+    bool admm_state = false;
+    double last_bytes = 0;
+
+    Impl(const DevGraph& graph, int d_, int qk_, const double* A_, hipStream_t s_,
+         const ccm_options& opt, double tol_, std::string& e)
+        : g(graph), d(d_), n(graph.n), m(graph.m), N(graph.n * d_), M(graph.m * d_), qk(qk_),
+          A(A_), s(s_), o(opt), tol(tol_), err(e) {
+        prof.on = o.profile != 0;
+        prof.s = s;
+    }
+    ~Impl() {
+        if (hs) (void)hipHostFree(hs);
+        if (hflag) (void)hipHostFree(hflag);
+    }
+
+    ccm_status alloc() {
+        const size_t vb = size_t(N) * 8, eb = size_t(M) * 8;
+        for (DevMem* b : {&bX, &bXt, &bG, &bGt, &bDinv, &bDinvt, &bTmp, &bTmp2, &cgx, &cgr, &cgu,
+                          &cgw, &cgp, &cgs})
+            HIPCHK(b->alloc(vb, s));
+        HIPCHK(bU.alloc(eb, s));
+        if (o.method == CCM_SSNAL) {
+            HIPCHK(bPi.alloc(eb, s));
+            HIPCHK(bPit.alloc(eb, s));
+            const int W = mask_words(d);
+            if (qk == kQ2) {
+                HIPCHK(al0.alloc(m * 8, s));
+                HIPCHK(al1.alloc(m * 8, s));
+            } else {
+                const int NB = qk == kQ1 ? 1 : 2;
+                HIPCHK(bi0.alloc(size_t(m) * W * NB * 8, s));
+                HIPCHK(bi1.alloc(size_t(m) * W * NB * 8, s));
+                if (qk == kQInf) {
+                    HIPCHK(cn0.alloc(m * 4, s));
+                    HIPCHK(cn1.alloc(m * 4, s));
+                }
+            }
+        } else if (o.method == CCM_ADMM) {
+            HIPCHK(bZ.alloc(eb, s));
+            HIPCHK(bL.alloc(eb, s));
+            HIPCHK(bQ.alloc(eb, s));
+            HIPCHK(bZold.alloc(eb, s));
+        } else {
+            HIPCHK(bZ.alloc(eb, s));  // momentum point V
+        }
+        HIPCHK(fused.alloc(std::max<int64_t>(m, 1) * 4, s));
+        HIPCHK(parent.alloc(n * 4, s));
+        HIPCHK(rank.alloc((n + 1) * 4, s));
+        ltemp_bytes = labels_temp_bytes(n);
+        HIPCHK(ltemp.alloc(ltemp_bytes, s));
+        const size_t pb = size_t(kMaxGrid) * 8 * 8;
+        for (DevMem* b : {&pe, &pet, &ps, &pst, &pt, &pk, &pm, &pm2, &pupd0, &pupd1, &pwu0, &pwu1})
+            HIPCHK(b->alloc(pb, s));
+        HIPCHK(dsc.alloc(kNS * 8, s));
+        HIPCHK(cgstate.alloc(8 * 8, s));
+        HIPCHK(cgflag.alloc(4 * 4, s));
+        HIPCHK(spread_work.alloc(size_t(spread_work_size(n, d)) * 8, s));
+        HIPCHK(hipHostMalloc((void**)&hs, kNS * 8, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&hflag, 4 * 4, hipHostMallocDefault));
+        std::memset(hs, 0, kNS * 8);
+        X = bX.as<double>();
+        Xt = bXt.as<double>();
+        G = bG.as<double>();
+        Gt = bGt.as<double>();
+        Dinv = bDinv.as<double>();
+        Dinvt = bDinvt.as<double>();
+        U = bU.as<double>();
+        Pi = bPi.as<double>();
+        Pit = bPit.as<double>();
+        pl = Payload{al0.as<double>(), bi0.as<uint64_t>(), cn0.as<int>()};
+        plt = Payload{al1.as<double>(), bi1.as<uint64_t>(), cn1.as<int>()};
+        cg.x = cgx.as<double>();
+        cg.r = cgr.as<double>();
+        cg.u = cgu.as<double>();
+        cg.w = cgw.as<double>();
+        cg.p = cgp.as<double>();
+        cg.s = cgs.as<double>();
+        cg.upd[0] = pupd0.as<double>();
+        cg.upd[1] = pupd1.as<double>();
+        cg.wu[0] = pwu0.as<double>();
+        cg.wu[1] = pwu1.as<double>();
+        cg.state = cgstate.as<double>();
+        cg.flag = cgflag.as<int>();
+        cg.nparts = cg_update_grid(N);
+        return CCM_OK;
+    }
+
+    // copy scalar slots [a, b) to the host and wait
+    ccm_status read(int a, int b) {
+        HIPCHK(hipMemcpyAsync(hs + a, dsc.as<double>() + a, size_t(b - a) * 8,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        prof.harvest();
+        return CCM_OK;
+    }
+    double* slot(int k) { return dsc.as<double>() + k; }
+
+    bool out_of_time() const {
+        if (!(o.time_budget_s > 0)) return false;
+        const double el = std::chrono::duration<double>(Clock::now() - t_start).count();
+        return el > o.time_budget_s;
+    }
+
+    // ---- set-up --------------------------------------------------------------
+    ccm_status setup(const double* Xw, const double* Uw) {
+        CHK(alloc());
+        // ||A||^2 and the data spread S (label threshold)
+        {
+            const int gp = launch_dot(A, A, N, pm.as<double>(), s);
+            launch_finalize(pm.as<double>(), gp, 1, slot(kNA), s);
+            launch_spread(A, n, d, spread_work.as<double>(), slot(kSP), s);
+            CHK(read(kNA, kSP + 1));
+            nA = std::sqrt(hs[kNA]);
+            spread = hs[kSP];
+        }
+        if (Xw) HIPCHK(hipMemcpyAsync(X, Xw, size_t(N) * 8, hipMemcpyDeviceToDevice, s));
+        else HIPCHK(hipMemcpyAsync(X, A, size_t(N) * 8, hipMemcpyDeviceToDevice, s));
+        if (Uw) {
+            HIPCHK(hipMemcpyAsync(U, Uw, size_t(M) * 8, hipMemcpyDeviceToDevice, s));
+            have_U = true;
+        } else {
+            launch_fill(U, M, 0.0, s);
+            have_U = false;
+        }
+        return CCM_OK;
+    }
+
+    // ---- shared pieces -------------------------------------------------------
+    void edge_pass(const double* Xc, double* Pic, Payload p, double gamma, double* part,
+                   int slot_out) {
+        Timed t(prof, CCM_K_EDGE);
+        const int gp = launch_edge_ssnal(g, d, qk, gamma, sigma, Xc, U, Pic, p, part, s);
+        launch_finalize(part, gp, kEdgeSsnalNV, slot(slot_out), s);
+    }
+    void scatter_grad(const double* Xc, const double* Pic, Payload p, double gamma, double* Gc,
+                      double* Dc, double* part, int slot_out) {
+        Timed t(prof, CCM_K_SCATTER);
+        const int gp = launch_scatter(g, d, qk, 1.0, Xc, -1.0, A, 1.0, Pic, Gc, true, p, gamma, sigma,
+                                      Dc, part, s);
+        launch_finalize(part, gp, kScatterNV, slot(slot_out), s);
+    }
+    Ev make_ev(int e, int sc) const {
+        Ev v;
+        v.bxpi = hs[e + 0];
+        v.pu2 = hs[e + 1];
+        v.bx2 = hs[e + 2];
+        v.pi2 = hs[e + 3];
+        v.nout = hs[e + 4];
+        v.G2 = hs[sc + 0];
+        v.hx = hs[sc + 1];
+        v.aBtPi = hs[sc + 2];
+        v.BtPi2 = hs[sc + 3];
+        // phi = 1/2||X-A||^2 + <BX, Pi> - ||Pi - U||^2 / (2 sigma)
+        v.phi = v.hx + v.bxpi - v.pu2 / (2.0 * sigma);
+        v.gn = std::sqrt(v.G2) / (1.0 + nA);
+        v.rp = std::sqrt(v.pu2) / (sigma * (1.0 + std::sqrt(v.bx2) + std::sqrt(v.pi2)));
+        return v;
+    }
+
+    double matvec_bytes(double nout) const {
+        // one-pass minimum traffic of a Newton matvec launch: read V, write
+        // out, incidence lists, and the per-edge payload (rows of Pi only for
+        // edges whose Jacobian is not the identity)
+        double b = 16.0 * double(N) + 4.0 * double(n + 1) + 16.0 * double(m);
+        if (qk == kQ2) b += 8.0 * double(m) + nout * (8.0 * d + 8.0);
+        else if (qk == kQ1) b += double(m) * mask_words(d) * 8.0;
+        else b += 4.0 * double(m) + nout * mask_words(d) * 16.0;
+        return b;
+    }
+
+    // Solve M x = b (M = I + sigma B^T P B for mode 0, I + sigma B^T B for
+    // mode 1) by Jacobi-preconditioned CG from x = 0; result in cg.x.
+    ccm_status cg_solve(int mode, const double* b, bool neg, const double* Dv, double thr,
+                        double gamma, const double* Pic, Payload p, int& iters) {
+        {
+            Timed t(prof, CCM_K_CGUPDATE);
+            launch_cg_init(N, b, neg, Dv, cg, s);
+        }
+        {
+            Timed t(prof, CCM_K_MATVEC);
+            cg.nparts_mv = launch_matvec(g, d, qk, mode, cg.u, Pic, p, gamma, sigma, 1.0, nullptr,
+                                         cg.w, cg.wu[0], CgSkip{}, s);
+        }
+        const int chunk = std::max(1, o.cg_chunk);
+        int j = 0;
+        hflag[0] = 0;
+        hflag[1] = 0;
+        while (j < o.cg_max_iter) {
+            for (int c = 0; c < chunk && j < o.cg_max_iter; ++c, ++j) {
+                {
+                    Timed t(prof, CCM_K_CGUPDATE);
+                    launch_cg_update(N, j, Dv, cg, thr, s);
+                }
+                Timed t(prof, CCM_K_MATVEC);
+                CgSkip sk;
+                sk.rr_partials = cg.upd[(j + 1) & 1];
+                sk.nparts = cg.nparts;
+                sk.thr = thr;
+                sk.done = cg.flag;
+                launch_matvec(g, d, qk, mode, cg.u, Pic, p, gamma, sigma, 1.0, nullptr, cg.w,
+                              cg.wu[(j + 1) & 1], sk, s);
+            }
+            HIPCHK(hipMemcpyAsync(hflag, cg.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            prof.harvest();
+            if (hflag[0]) break;
+        }
+        iters = hflag[0] ? hflag[1] : j;
+        return CCM_OK;
+    }
+
+    // ---- KKT of (X, Uc) with Uc feasible up to rounding -------------------------
+    // scalars: scatter at (X, Uc) in kS.., KKT edge pass in kK..
+    ccm_status kkt_of(const double* Uc, double gamma, double* Gout, double (&res)[7]) {
+        {
+            Timed t(prof, CCM_K_SCATTER);
+            const int gp = launch_scatter(g, d, qk, 1.0, X, -1.0, A, 1.0, Uc, Gout, false, Payload{},
+                                          gamma, sigma, nullptr, ps.as<double>(), s);
+            launch_finalize(ps.as<double>(), gp, kScatterNV, slot(kS), s);
+        }
+        {
+            Timed t(prof, CCM_K_EDGE);
+            const int gp = launch_edge_kkt(g, d, qk, gamma, X, Uc, nullptr, pk.as<double>(), s);
+            launch_finalize(pk.as<double>(), gp, kEdgeKktNV, slot(kK), s);
+        }
+        CHK(read(kS, kK + kEdgeKktNV));
+        kkt_from_slots(res);
+        return CCM_OK;
+    }
+    // residuals with the scatter values of `ev` (taken at (X, U)) and the KKT
+    // edge pass in the kK slots
+    void kkt_from(const Ev& ev, double (&res)[7]) {
+        const double nbx = std::sqrt(hs[kK + 1]), nu = std::sqrt(hs[kK + 2]);
+        const double RD = ev.gn;
+        const double RC = std::sqrt(hs[kK + 0]) / (1.0 + nbx + nu);
+        const double RU = std::sqrt(hs[kK + 3]) / (1.0 + nu);
+        const double fp = ev.hx + hs[kK + 4];
+        const double fd = ev.aBtPi - 0.5 * ev.BtPi2;
+        const double eta = std::fabs(fp - fd) / (1.0 + std::fabs(fp) + std::fabs(fd));
+        res[0] = RD;
+        res[1] = RC;
+        res[2] = RU;
+        res[3] = eta;
+        res[4] = fp;
+        res[5] = fd;
+        res[6] = std::max(RD, std::max(RC, RU));
+    }
+    void kkt_from_slots(double (&res)[7]) {
+        const double RD = std::sqrt(hs[kS]) / (1.0 + nA);
+        const double nbx = std::sqrt(hs[kK + 1]), nu = std::sqrt(hs[kK + 2]);
+        const double RC = std::sqrt(hs[kK + 0]) / (1.0 + nbx + nu);
+        const double RU = std::sqrt(hs[kK + 3]) / (1.0 + nu);
+        const double fp = hs[kS + 1] + hs[kK + 4];
+        const double fd = hs[kS + 2] - 0.5 * hs[kS + 3];
+        const double eta = std::fabs(fp - fd) / (1.0 + std::fabs(fp) + std::fabs(fd));
+        res[0] = RD;
+        res[1] = RC;
+        res[2] = RU;
+        res[3] = eta;
+        res[4] = fp;
+        res[5] = fd;
+        res[6] = std::max(RD, std::max(RC, RU));
+    }
+
+    // ---- SSNAL at one gamma ------------------------------------------------------
+    ccm_status ssnal(double gamma, int& status, ccm_stats& st, double (&res)[7]) {
+        const double mu = 1e-4, ls_slack = 1e-14;
+        double rp_prev = INFINITY;
+        status = CCM_MAX_ITER;
+        bool numerical = false;
+        for (int k = 0; k < o.max_outer; ++k) {
+            st.outer++;
+            edge_pass(X, Pi, pl, gamma, pe.as<double>(), kE);
+            scatter_grad(X, Pi, pl, gamma, G, Dinv, ps.as<double>(), kS);
+            CHK(read(kE, kS + kScatterNV));
+            Ev ev = make_ev(kE, kS);
+            last_bytes = matvec_bytes(ev.nout);
+            for (int it = 0; it < o.max_newton; ++it) {
+                if (!std::isfinite(ev.phi) || !std::isfinite(ev.gn)) {
+                    numerical = true;
+                    break;
+                }
+                if (ev.gn <= std::max(0.5 * tol, 0.2 * ev.rp)) break;
+                if (out_of_time()) {
+                    status = CCM_TIMEOUT;
+                    return CCM_OK;
+                }
+                // Newton direction: (I + sigma B^T P B) D = -G
+                const double rtol = std::min(0.1, std::pow(ev.gn, 0.2));
+                const double thr = rtol * rtol * ev.G2;
+                int iters = 0;
+                CHK(cg_solve(0, G, true, Dinv, thr, gamma, Pi, pl, iters));
+                st.cg += iters;
+                st.newton++;
+                // Armijo backtracking on phi
+                double alpha = 1.0;
+                bool accepted = false;
+                Ev evt;
+                for (int t = 0; t < 40; ++t) {
+                    st.linesearch++;
+                    {
+                        Timed tt(prof, CCM_K_OTHER);
+                        const int gp = launch_trial(N, X, cg.x, alpha, A, G, Xt, pt.as<double>(), s);
+                        launch_finalize(pt.as<double>(), gp, kAxpyNV, slot(kT), s);
+                    }
+                    edge_pass(Xt, Pit, plt, gamma, pet.as<double>(), kET);
+                    // speculative gradient at the trial point (used if accepted)
+                    scatter_grad(Xt, Pit, plt, gamma, Gt, Dinvt, pst.as<double>(), kST);
+                    CHK(read(kT, kST + kScatterNV));
+                    double slope = hs[kT + 1];
+                    if (t == 0 && !(slope < 0.0)) {
+                        // not a descent direction: fall back to steepest descent
+                        launch_axpby(-1.0, G, 0.0, G, cg.x, N, s);
+                        alpha = 1.0;
+                        continue;
+                    }
+                    evt = make_ev(kET, kST);
+                    const double slack = ls_slack * (1.0 + std::fabs(ev.phi));
+                    if (evt.phi <= ev.phi + mu * alpha * slope + slack) {
+                        accepted = true;
+                        break;
+                    }
+                    alpha *= 0.5;
+                }
+                (void)accepted;  // after 40 halvings the last (tiny) step is taken
+                std::swap(X, Xt);
+                std::swap(Pi, Pit);
+                std::swap(pl, plt);
+                std::swap(G, Gt);
+                std::swap(Dinv, Dinvt);
+                ev = evt;
+                last_bytes = matvec_bytes(ev.nout);
+            }
+            if (numerical) break;
+            // multiplier update U <- Pi_C(U + sigma B X), already in Pi
+            std::swap(U, Pi);
+            have_U = true;
+            // KKT at (X, U): R_D from the last gradient, the rest from one pass
+            {
+                Timed t(prof, CCM_K_EDGE);
+                const int gp = launch_edge_kkt(g, d, qk, gamma, X, U, nullptr, pk.as<double>(), s);
+                launch_finalize(pk.as<double>(), gp, kEdgeKktNV, slot(kK), s);
+            }
+            CHK(read(kK, kK + kEdgeKktNV));
+            kkt_from(ev, res);
+            if (!std::isfinite(res[6])) {
+                numerical = true;
+                break;
+            }
+            if (res[6] <= tol) {
+                status = CCM_CONVERGED;
+                break;
+            }
+            if (out_of_time()) {
+                status = CCM_TIMEOUT;
+                break;
+            }
+            if (k >= 1 && ev.rp > 0.9 * rp_prev) sigma = std::min(o.sigma_max, 2.0 * sigma);
+            rp_prev = ev.rp;
+        }
+        if (numerical) status = CCM_NUMERICAL;
+        return CCM_OK;
+    }
+
+    // ---- ADMM at one gamma -------------------------------------------------------
+    ccm_status admm(double gamma, int& status, ccm_stats& st, double (&res)[7]) {
+        const int ce = std::max(1, o.check_every);
+        const int balance = 50;
+        double* Z = bZ.as<double>();
+        double* L = bL.as<double>();
+        double* Q = bQ.as<double>();
+        double* R = bTmp.as<double>();
+        double* T = bTmp2.as<double>();
+        status = CCM_MAX_ITER;
+        if (!admm_state) {
+            // cold start: Z = B X, L = 0
+            launch_gather(g, d, X, Z, s);
+            launch_fill(L, M, 0.0, s);
+            admm_state = true;
+        }
+        launch_axpby(sigma, Z, -1.0, L, Q, M, s);
+        launch_lap_dinv(g, d, 1.0, sigma, Dinv, s);
+        const double thr_abs = 0.01 * tol * (1.0 + nA);
+        for (int it = 1; it <= o.max_iter; ++it) {
+            st.outer++;
+            {
+                Timed t(prof, CCM_K_SCATTER);
+                launch_scatter(g, d, qk, 0.0, nullptr, 1.0, A, 1.0, Q, R, false, Payload{}, gamma,
+                               sigma, nullptr, ps.as<double>(), s);
+            }
+            {
+                Timed t(prof, CCM_K_MATVEC);
+                launch_matvec(g, d, qk, 1, X, nullptr, Payload{}, gamma, sigma, 1.0, nullptr, T,
+                              pm2.as<double>(), CgSkip{}, s);
+            }
+            launch_sub(R, T, R, N, s);  // residual of the warm start
+            int iters = 0;
+            CHK(cg_solve(1, R, false, Dinv, thr_abs * thr_abs, gamma, nullptr, Payload{}, iters));
+            st.cg += iters;
+            launch_axpy(X, 1.0, cg.x, N, s);
+            const bool check = (it % ce) == 0;
+            const bool bal = (it % balance) == 0;
+            if (bal) launch_copy(Z, bZold.as<double>(), M, s);
+            {
+                Timed t(prof, CCM_K_EDGE);
+                const int gp = launch_edge_admm(g, d, qk, gamma, sigma, o.tau, X, Z, L, Q,
+                                                check ? U : nullptr, pe.as<double>(), s);
+                launch_finalize(pe.as<double>(), gp, kEdgeAdmmNV, slot(kM), s);
+            }
+            if (check) {
+                CHK(kkt_of(U, gamma, G, res));
+                if (!std::isfinite(res[6])) {
+                    status = CCM_NUMERICAL;
+                    break;
+                }
+                if (res[6] <= tol) {
+                    status = CCM_CONVERGED;
+                    break;
+                }
+                if (out_of_time()) {
+                    status = CCM_TIMEOUT;
+                    break;
+                }
+            }
+            if (bal) {
+                launch_sub(Z, bZold.as<double>(), bZold.as<double>(), M, s);
+                const int gp = launch_scatter(g, d, qk, 0.0, nullptr, 0.0, nullptr, 1.0,
+                                              bZold.as<double>(), T, false, Payload{}, gamma,
+                                              sigma, nullptr, pm2.as<double>(), s);
+                launch_finalize(pm2.as<double>(), gp, kScatterNV, slot(kM + 4), s);
+                CHK(read(kM, kM + 8));
+                const double rp = std::sqrt(hs[kM + 0]);
+                const double rd = sigma * std::sqrt(hs[kM + 4]);
+                double ns = sigma;
+                if (rp > 10.0 * rd) ns = 2.0 * sigma;
+                else if (rd > 10.0 * rp) ns = 0.5 * sigma;
+                if (ns != sigma) {
+                    sigma = ns;
+                    launch_axpby(sigma, Z, -1.0, L, Q, M, s);
+                    launch_lap_dinv(g, d, 1.0, sigma, Dinv, s);
+                }
+            }
+        }
+        if (status != CCM_CONVERGED) CHK(kkt_last_admm(gamma, res));
+        return CCM_OK;
+    }
+    ccm_status kkt_last_admm(double gamma, double (&res)[7]) {
+        // U <- Pi_C(L) through the KKT edge pass with U = L (writes Pi_C(L))
+        {
+            Timed t(prof, CCM_K_EDGE);
+            const int gp = launch_edge_kkt(g, d, qk, gamma, X, bL.as<double>(), U,
+                                           pk.as<double>(), s);
+            launch_finalize(pk.as<double>(), gp, kEdgeKktNV, slot(kK), s);
+        }
+        return kkt_of(U, gamma, G, res);
+    }
+
+    // ---- fast AMA at one gamma ----------------------------------------------------
+    ccm_status ama(double gamma, int& status, ccm_stats& st, double (&res)[7]) {
+        const int ce = std::max(1, o.check_every);
+        double* V = bZ.as<double>();
+        status = CCM_MAX_ITER;
+        // U is projected onto the new (larger) balls first, V = U
+        launch_edge_kkt(g, d, qk, gamma, X, U, V, pk.as<double>(), s);
+        launch_copy(V, U, M, s);
+        const double nu = 1.0 / (2.0 * double(std::max(1, g.max_deg)));
+        double t = 1.0;
+        bool restart_next = true;
+        for (int it = 1; it <= o.max_iter; ++it) {
+            st.outer++;
+            // X = A - B^T V
+            {
+                Timed tt(prof, CCM_K_SCATTER);
+                launch_scatter(g, d, qk, 0.0, nullptr, 1.0, A, -1.0, V, X, false, Payload{},
+                               gamma, sigma, nullptr, ps.as<double>(), s);
+            }
+            double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+            double beta = restart_next ? 0.0 : (t - 1.0) / tn;
+            {
+                Timed tt(prof, CCM_K_EDGE);
+                const int gp = launch_edge_ama(g, d, qk, gamma, nu, beta, X, U, V, pe.as<double>(),
+                                               s);
+                launch_finalize(pe.as<double>(), gp, kEdgeAmaNV, slot(kM), s);
+            }
+            CHK(read(kM, kM + 2));
+            if (hs[kM + 0] > 0.0) {
+                // momentum points uphill: restart from the new point
+                launch_copy(U, V, M, s);
+                t = 1.0;
+                restart_next = false;
+            } else {
+                t = restart_next ? 1.0 : tn;
+                restart_next = false;
+            }
+            if ((it % ce) == 0) {
+                // X = A - B^T U for the test
+                launch_scatter(g, d, qk, 0.0, nullptr, 1.0, A, -1.0, U, X, false, Payload{},
+                               gamma, sigma, nullptr, ps.as<double>(), s);
+                CHK(kkt_of(U, gamma, G, res));
+                if (!std::isfinite(res[6])) {
+                    status = CCM_NUMERICAL;
+                    break;
+                }
+                if (res[6] <= tol) {
+                    status = CCM_CONVERGED;
+                    break;
+                }
+                if (out_of_time()) {
+                    status = CCM_TIMEOUT;
+                    break;
+                }
+            }
+        }
+        if (status != CCM_CONVERGED) {
+            launch_scatter(g, d, qk, 0.0, nullptr, 1.0, A, -1.0, U, X, false, Payload{}, gamma,
+                           sigma, nullptr, ps.as<double>(), s);
+            CHK(kkt_of(U, gamma, G, res));
+        }
+        return CCM_OK;
+    }
+
+    ccm_status labels(int* lab_out, int* nclus_host) {
+        Timed t(prof, CCM_K_OTHER);
+        const double thr = 1e-5 * (1.0 + spread);
+        if (m > 0) launch_fused_flags(g, d, X, thr, fused.as<int>(), s);
+        int* lab = lab_out;
+        DevMem scratch;
+        if (!lab) {
+            HIPCHK(scratch.alloc(n * 4, s));
+            lab = scratch.as<int>();
+        }
+        launch_labels(n, m, g.src, g.dst, fused.as<int>(), parent.as<int>(), rank.as<int>(),
+                      ltemp.p, ltemp_bytes, lab, cgflag.as<int>() + 2, s);
+        HIPCHK(hipMemcpyAsync(hflag + 2, cgflag.as<int>() + 2, sizeof(int), hipMemcpyDeviceToHost,
+                              s));
+        HIPCHK(hipStreamSynchronize(s));
+        prof.harvest();
+        if (nclus_host) *nclus_host = hflag[2];
+        return CCM_OK;
+    }
+};
+
+Solver::Solver(const DevGraph& g, int d, int qk, const double* A, hipStream_t s,
+               const ccm_options& o, double tol, std::string& err)
+    : impl_(new Impl(g, d, qk, A, s, o, tol, err)) {}
+Solver::~Solver() { delete impl_; }
+
+ccm_status Solver::run_path(const double* gammas, int T, const double* Xw, const double* Uw,
+                            double* X_out, double* U_out, int* labels_out, int* n_clusters,
+                            double* kkt, int* status, ccm_stats* stats) {
+    Impl& I = *impl_;
+    std::string& err = I.err;
+    I.t_start = Clock::now();
+    CHK(I.setup(Xw, Uw));
+    I.sigma = I.o.sigma0;
+    for (int t = 0; t < T; ++t) {
+        const double gamma = gammas[t];
+        const auto t0 = Clock::now();
+        ccm_stats st;
+        std::memset(&st, 0, sizeof(st));
+        int stat = CCM_CONVERGED;
+        double res[7] = {0, 0, 0, 0, 0, 0, 0};
+        if (gamma == 0.0 || I.m == 0) {
+            // the model reduces to X = A (and U = 0 is a dual solution)
+            HIPCHK(hipMemcpyAsync(I.X, I.A, size_t(I.N) * 8, hipMemcpyDeviceToDevice, I.s));
+            launch_fill(I.U, I.M, 0.0, I.s);
+            I.admm_state = false;
+            // f_p = f_d = 0 and every residual is 0
+        } else if (I.o.method == CCM_SSNAL) {
+            CHK(I.ssnal(gamma, stat, st, res));
+        } else if (I.o.method == CCM_ADMM) {
+            CHK(I.admm(gamma, stat, st, res));
+        } else {
+            CHK(I.ama(gamma, stat, st, res));
+        }
+        if (X_out)
+            HIPCHK(hipMemcpyAsync(X_out + size_t(t) * I.N, I.X, size_t(I.N) * 8,
+                                  hipMemcpyDeviceToDevice, I.s));
+        if (U_out && I.M > 0)
+            HIPCHK(hipMemcpyAsync(U_out + size_t(t) * I.M, I.U, size_t(I.M) * 8,
+                                  hipMemcpyDeviceToDevice, I.s));
+        int nc = 0;
+        CHK(I.labels(labels_out ? labels_out + size_t(t) * I.n : nullptr, &nc));
+        if (n_clusters) n_clusters[t] = nc;
+        if (kkt) {
+            kkt[4 * t + 0] = res[0];
+            kkt[4 * t + 1] = res[1];
+            kkt[4 * t + 2] = res[2];
+            kkt[4 * t + 3] = res[3];
+        }
+        if (status) status[t] = stat;
+        st.seconds = std::chrono::duration<double>(Clock::now() - t0).count();
+        st.f_p = res[4];
+        st.f_d = res[5];
+        st.sigma = I.sigma;
+        st.edge_bytes = I.last_bytes;
+        I.prof.take(st);
+        if (stats) stats[t] = st;
+    }
+    HIPCHK(hipStreamSynchronize(I.s));
+    return CCM_OK;
+}
+
+}  // namespace ccm

@@ -1,0 +1,358 @@
+// Element-wise and reduction kernels on n x d vertex arrays: the conjugate
+// gradient vector updates, line-search trial points, partial-sum
+// finalisation and small utilities.
+#include "launch.hpp"
+
+namespace ccm {
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_cg_init(int64_t N, const double* __restrict__ b,
+                                                    double sgn, const double* __restrict__ Dinv,
+                                                    double* __restrict__ x, double* __restrict__ r,
+                                                    double* __restrict__ u, double* __restrict__ p,
+                                                    double* __restrict__ s,
+                                                    double* __restrict__ upd0, int* flag) {
+    double acc[2] = {0.0, 0.0};
+    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
+         k += int64_t(gridDim.x) * kBlock) {
+        const double rv = sgn * b[k];
+        const double uv = Dinv[k] * rv;
+        r[k] = rv;
+        u[k] = uv;
+        x[k] = 0.0;
+        p[k] = 0.0;
+        s[k] = 0.0;
+        acc[0] += rv * uv;
+        acc[1] += rv * rv;
+    }
+    block_reduce_store<2>(acc, upd0 + blockIdx.x * 2);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        flag[0] = 0;
+        flag[1] = 0;
+    }
+}
+
+// Iteration j of preconditioned CG in the Chronopoulos-Gear arrangement, which
+// needs one global reduction point per iteration: the dot products r.u (from
+// this kernel) and w.u (from the matvec w = A u that follows it) are both
+// consumed by the next update.  With gamma_j = r_j.u_j, delta_j = w_j.u_j:
+//   beta_j  = gamma_j / gamma_{j-1},  alpha_j = gamma_j / (delta_j - beta_j gamma_j / alpha_{j-1})
+//   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,  u = M^{-1} r
+// (j = 0: beta = 0, alpha = gamma_0 / delta_0).  Every block re-reduces the
+// partials in the same order, so all blocks agree bit for bit on alpha and
+// beta; scalars and partials alternate between two slots by parity of j.
+__global__ __launch_bounds__(kBlock) void k_cg_update(
+    int64_t N, int j, const double* __restrict__ Dinv, double* __restrict__ x,
+    double* __restrict__ r, double* __restrict__ u, const double* __restrict__ w,
+    double* __restrict__ p, double* __restrict__ s, const double* __restrict__ upd_prev,
+    double* __restrict__ upd_next, const double* __restrict__ wu, int nparts_upd, int nparts_mv,
+    double* __restrict__ state, int* flag, double thr) {
+    if (flag[0]) return;
+    const int par = j & 1;
+    const double rr = block_sum_partials(upd_prev, nparts_upd, 2, 1);
+    if (rr <= thr) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            flag[0] = 1;
+            flag[1] = j;
+        }
+        return;
+    }
+    const double gam = block_sum_partials(upd_prev, nparts_upd, 2, 0);
+    const double del = block_sum_partials(wu, nparts_mv, 1, 0);
+    double alpha, beta;
+    if (j == 0) {
+        beta = 0.0;
+        alpha = gam / del;
+    } else {
+        const double gp = state[par * 2 + 0];
+        const double ap = state[par * 2 + 1];
+        beta = gam / gp;
+        alpha = gam / (del - beta * gam / ap);
+    }
+    if (!(alpha > 0.0) || !isfinite(alpha) || !isfinite(beta)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            flag[0] = 2;
+            flag[1] = j;
+        }
+        return;
+    }
+    double acc[2] = {0.0, 0.0};
+    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
+         k += int64_t(gridDim.x) * kBlock) {
+        const double pk = u[k] + beta * p[k];
+        const double sk = w[k] + beta * s[k];
+        x[k] += alpha * pk;
+        const double rk = r[k] - alpha * sk;
+        const double uk = Dinv[k] * rk;
+        p[k] = pk;
+        s[k] = sk;
+        r[k] = rk;
+        u[k] = uk;
+        acc[0] += rk * uk;
+        acc[1] += rk * rk;
+    }
+    block_reduce_store<2>(acc, upd_next + blockIdx.x * 2);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        state[(par ^ 1) * 2 + 0] = gam;
+        state[(par ^ 1) * 2 + 1] = alpha;
+        flag[1] = j + 1;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_trial(int64_t N, const double* __restrict__ X,
+                                                  const double* __restrict__ D, double alpha,
+                                                  const double* __restrict__ A,
+                                                  const double* __restrict__ G,
+                                                  double* __restrict__ Xt,
+                                                  double* __restrict__ partials) {
+    double acc[kAxpyNV] = {0.0, 0.0};
+    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
+         k += int64_t(gridDim.x) * kBlock) {
+        const double dk = D[k];
+        const double xt = X[k] + alpha * dk;
+        Xt[k] = xt;
+        const double e = xt - A[k];
+        acc[0] += 0.5 * e * e;
+        acc[1] += G[k] * dk;
+    }
+    block_reduce_store<kAxpyNV>(acc, partials + blockIdx.x * kAxpyNV);
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials,
+                                                     int nparts, int nv, double* __restrict__ out) {
+    for (int c = 0; c < nv; ++c) {
+        const double t = block_sum_partials(partials, nparts, nv, c);
+        if (threadIdx.x == 0) out[c] = t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(double* __restrict__ x, int64_t N, double v) {
+    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
+         k += int64_t(gridDim.x) * kBlock)
+        x[k] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpy(double* __restrict__ x, double alpha,
+                                                 const double* __restrict__ y, int64_t N) {
+    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
+         k += int64_t(gridDim.x) * kBlock)
+        x[k] += alpha * y[k];
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpby(double a, const double* __restrict__ x, double b,
+                                                  const double* __restrict__ y,
+                                                  double* __restrict__ o, int64_t N) {
+    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
+         k += int64_t(gridDim.x) * kBlock)
+        o[k] = a * x[k] + b * y[k];
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot(const double* __restrict__ x,
+                                                const double* __restrict__ y, int64_t N,
+                                                double* __restrict__ partials) {
+    double acc[1] = {0.0};
+    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
+         k += int64_t(gridDim.x) * kBlock)
+        acc[0] += x[k] * y[k];
+    block_reduce_store<1>(acc, partials + blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy(const double* __restrict__ a,
+                                                 double* __restrict__ b, int64_t N) {
+    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
+         k += int64_t(gridDim.x) * kBlock)
+        b[k] = a[k];
+}
+
+__global__ __launch_bounds__(kBlock) void k_sub(const double* __restrict__ a,
+                                                const double* __restrict__ b,
+                                                double* __restrict__ o, int64_t N) {
+    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
+         k += int64_t(gridDim.x) * kBlock)
+        o[k] = a[k] - b[k];
+}
+
+__global__ __launch_bounds__(kBlock) void k_lap_dinv(int64_t n, int d,
+                                                     const int* __restrict__ inc_ptr, double c0,
+                                                     double sigma, double* __restrict__ Dinv) {
+    const int64_t N = n * d;
+    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
+         k += int64_t(gridDim.x) * kBlock) {
+        const int64_t i = k / d;
+        Dinv[k] = 1.0 / (c0 + sigma * double(inc_ptr[i + 1] - inc_ptr[i]));
+    }
+}
+
+// column sums of A over a contiguous range of rows per block
+__global__ __launch_bounds__(kBlock) void k_colsum(const double* __restrict__ A, int64_t n, int d,
+                                                   double* __restrict__ part) {
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = int64_t(blockIdx.x) * per;
+    const int64_t r1 = r0 + per < n ? r0 + per : n;
+    for (int k = threadIdx.x; k < d; k += blockDim.x) {
+        double t = 0.0;
+        for (int64_t i = r0; i < r1; ++i) t += A[i * d + k];
+        part[int64_t(blockIdx.x) * d + k] = t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_colmean(const double* __restrict__ part, int nparts,
+                                                    int64_t n, int d, double* __restrict__ mean) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d; k += gridDim.x * blockDim.x) {
+        double t = 0.0;
+        for (int p = 0; p < nparts; ++p) t += part[int64_t(p) * d + k];
+        mean[k] = t / double(n);
+    }
+}
+
+// per-block max over rows of ||a_i - mean||^2 (max is order independent)
+__global__ __launch_bounds__(kBlock) void k_rowdev_max(const double* __restrict__ A, int64_t n,
+                                                       int d, const double* __restrict__ mean,
+                                                       double* __restrict__ bmax) {
+    double best = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * kBlock) {
+        double t = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double e = A[i * d + k] - mean[k];
+            t += e * e;
+        }
+        best = fmax(best, t);
+    }
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = best;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bmax[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_max_sqrt(const double* __restrict__ bmax, int nb,
+                                                     double* __restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double t = 0.0;
+        for (int b = 0; b < nb; ++b) t = fmax(t, bmax[b]);
+        out[0] = sqrt(t);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_stream_copy(const uint4* __restrict__ a,
+                                                        uint4* __restrict__ b, int64_t N) {
+    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
+         k += int64_t(gridDim.x) * kBlock)
+        b[k] = a[k];
+}
+
+__global__ void k_copy_bytes(const unsigned char* __restrict__ a, unsigned char* __restrict__ b,
+                             int64_t N) {
+    for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < N;
+         k += int64_t(gridDim.x) * blockDim.x)
+        b[k] = a[k];
+}
+
+constexpr int kSpreadBlocks = 128;
+
+}  // namespace
+
+int cg_update_grid(int64_t N) { return flat_grid(N); }
+
+void launch_cg_init(int64_t N, const double* b, bool neg, const double* Dinv, CgBufs& cg,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_init, dim3(flat_grid(N)), dim3(kBlock), 0, s, N, b, neg ? -1.0 : 1.0,
+                       Dinv, cg.x, cg.r, cg.u, cg.p, cg.s, cg.upd[0], cg.flag);
+}
+
+void launch_cg_update(int64_t N, int j, const double* Dinv, CgBufs& cg, double thr,
+                      hipStream_t s) {
+    const int par = j & 1;
+    hipLaunchKernelGGL(k_cg_update, dim3(flat_grid(N)), dim3(kBlock), 0, s, N, j, Dinv, cg.x, cg.r,
+                       cg.u, cg.w, cg.p, cg.s, cg.upd[par], cg.upd[par ^ 1], cg.wu[par], cg.nparts,
+                       cg.nparts_mv, cg.state, cg.flag, thr);
+}
+
+int launch_trial(int64_t N, const double* X, const double* D, double alpha, const double* A,
+                 const double* G, double* Xt, double* partials, hipStream_t s) {
+    const int grid = flat_grid(N);
+    hipLaunchKernelGGL(k_trial, dim3(grid), dim3(kBlock), 0, s, N, X, D, alpha, A, G, Xt,
+                       partials);
+    return grid;
+}
+
+void launch_finalize(const double* partials, int nparts, int nv, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, partials, nparts, nv, out);
+}
+
+void launch_fill(double* x, int64_t N, double v, hipStream_t s) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_fill, dim3(flat_grid(N)), dim3(kBlock), 0, s, x, N, v);
+}
+
+void launch_axpy(double* x, double alpha, const double* y, int64_t N, hipStream_t s) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_axpy, dim3(flat_grid(N)), dim3(kBlock), 0, s, x, alpha, y, N);
+}
+
+void launch_axpby(double a, const double* x, double b, const double* y, double* out, int64_t N,
+                  hipStream_t s) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_axpby, dim3(flat_grid(N)), dim3(kBlock), 0, s, a, x, b, y, out, N);
+}
+
+int launch_dot(const double* x, const double* y, int64_t N, double* partials, hipStream_t s) {
+    const int g = flat_grid(N);
+    hipLaunchKernelGGL(k_dot, dim3(g), dim3(kBlock), 0, s, x, y, N, partials);
+    return g;
+}
+
+void launch_copy(const double* a, double* b, int64_t N, hipStream_t s) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_copy, dim3(flat_grid(N)), dim3(kBlock), 0, s, a, b, N);
+}
+
+void launch_sub(const double* a, const double* b, double* out, int64_t N, hipStream_t s) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_sub, dim3(flat_grid(N)), dim3(kBlock), 0, s, a, b, out, N);
+}
+
+void launch_lap_dinv(const DevGraph& g, int d, double c0, double sigma, double* Dinv,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_lap_dinv, dim3(flat_grid(g.n * d)), dim3(kBlock), 0, s, g.n, d,
+                       g.inc_ptr, c0, sigma, Dinv);
+}
+
+int spread_work_size(int64_t n, int d) { return kSpreadBlocks * d + d + kSpreadBlocks; }
+
+void launch_spread(const double* A, int64_t n, int d, double* work, double* out, hipStream_t s) {
+    double* part = work;
+    double* mean = work + int64_t(kSpreadBlocks) * d;
+    double* bmax = mean + d;
+    hipLaunchKernelGGL(k_colsum, dim3(kSpreadBlocks), dim3(kBlock), 0, s, A, n, d, part);
+    hipLaunchKernelGGL(k_colmean, dim3((d + kBlock - 1) / kBlock), dim3(kBlock), 0, s, part,
+                       kSpreadBlocks, n, d, mean);
+    hipLaunchKernelGGL(k_rowdev_max, dim3(kSpreadBlocks), dim3(kBlock), 0, s, A, n, d, mean, bmax);
+    hipLaunchKernelGGL(k_max_sqrt, dim3(1), dim3(kBlock), 0, s, bmax, kSpreadBlocks, out);
+}
+
+void launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s) {
+    const int64_t n16 = bytes / 16;
+    if (n16 > 0 && (reinterpret_cast<uintptr_t>(src) % 16 == 0) &&
+        (reinterpret_cast<uintptr_t>(dst) % 16 == 0)) {
+        int64_t g = (n16 + kBlock - 1) / kBlock;
+        if (g > 8192) g = 8192;
+        hipLaunchKernelGGL(k_stream_copy, dim3(g), dim3(kBlock), 0, s,
+                           reinterpret_cast<const uint4*>(src), reinterpret_cast<uint4*>(dst), n16);
+        const int64_t rest = bytes - n16 * 16;
+        if (rest > 0)
+            hipLaunchKernelGGL(k_copy_bytes, dim3(1), dim3(64), 0, s,
+                               reinterpret_cast<const unsigned char*>(src) + n16 * 16,
+                               reinterpret_cast<unsigned char*>(dst) + n16 * 16, rest);
+    } else if (bytes > 0) {
+        hipLaunchKernelGGL(k_copy_bytes, dim3(1024), dim3(kBlock), 0, s,
+                           reinterpret_cast<const unsigned char*>(src),
+                           reinterpret_cast<unsigned char*>(dst), bytes);
+    }
+}
+
+}  // namespace ccm

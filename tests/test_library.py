@@ -1,0 +1,32 @@
+"""CPU checks of the built library: it loads and exports every entry point
+that include/ccm.h declares (no device calls)."""
+import ctypes
+import os
+import re
+
+import paper_2501_15964_amd as ccm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "ccm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ccm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    L = ccm.lib()
+    names = declared_symbols()
+    assert "ccm_solve_path" in names and "ccm_build_knn_graph" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(ccm.EXPORTED_SYMBOLS) == names
+
+
+def test_struct_sizes():
+    assert ctypes.sizeof(ccm.CcmOptions) == 64
+    assert ctypes.sizeof(ccm.CcmStats) == 136
+    o = ccm.ccm_default_options()
+    assert o.method == 0 and o.max_outer == 300 and o.cg_max_iter == 500
+    assert ccm.ccm_version().startswith("libccm")
