@@ -98,7 +98,14 @@ typedef struct {
     double sigma;                           /* penalty at exit */
     double kern_ms[CCM_NK];                 /* profile = 1: summed kernel time per class */
     int64_t kern_calls[CCM_NK];             /* profile = 1: launches per class */
-    double edge_bytes;                      /* algorithmic HBM bytes of one matvec launch */
+    double matvec_bytes;                    /* algorithmic bytes moved by the Newton / CG
+                                               matvec launches of this gamma (each launch:
+                                               read V once, write the output once, the
+                                               incidence lists, and the per-edge Jacobian
+                                               payload of edges with P != I) */
+    int64_t matvec_launches;                /* matvec launches that did work (launches
+                                               issued after CG convergence return at once
+                                               and are timed in class CCM_K_OTHER) */
 } ccm_stats;
 
 /* ---------------------------------------------------------------------------

@@ -63,14 +63,15 @@ class CcmStats(ctypes.Structure):
         ("seconds", ctypes.c_double), ("f_p", ctypes.c_double), ("f_d", ctypes.c_double),
         ("sigma", ctypes.c_double),
         ("kern_ms", ctypes.c_double * CCM_NK), ("kern_calls", ctypes.c_int64 * CCM_NK),
-        ("edge_bytes", ctypes.c_double),
+        ("matvec_bytes", ctypes.c_double), ("matvec_launches", ctypes.c_int64),
     ]
 
     def as_dict(self):
         return dict(outer=self.outer, newton=self.newton, cg=self.cg,
                     linesearch=self.linesearch, seconds=self.seconds, f_p=self.f_p,
                     f_d=self.f_d, sigma=self.sigma, kern_ms=list(self.kern_ms),
-                    kern_calls=list(self.kern_calls), edge_bytes=self.edge_bytes)
+                    kern_calls=list(self.kern_calls), matvec_bytes=self.matvec_bytes,
+                    matvec_launches=self.matvec_launches)
 
 
 _lib = None

@@ -184,7 +184,7 @@ ccm_status ccm_solve_path(const double* A, int64_t n, int64_t d, const int32_t* 
     if (n_gamma == 0) return CCM_OK;
     std::string err;
     OwnedGraph og;
-    st = graph_build(src, dst, w, m, n, false, stream, og, err);
+    st = graph_build(src, dst, w, m, n, int(d), false, stream, og, err);
     if (st != CCM_OK) return fail(st, err);
     Solver solver(og.g, int(d), qk, A, stream, o, tol, err);
     st = solver.run_path(gammas_host, n_gamma, X_warm, U_warm, X_out, U_out, labels_out,
@@ -251,10 +251,10 @@ ccm_status ccm_op_scatter(const double* Z, int64_t m, int64_t d, const int32_t* 
         HIPCHK_API(wbuf.alloc(size_t(m) * 8, stream));
         launch_fill(wbuf.as<double>(), m, 1.0, stream);
     }
-    st = graph_build(src, dst, wbuf.as<double>(), m, n, true, stream, og, err);
+    st = graph_build(src, dst, wbuf.as<double>(), m, n, int(d), true, stream, og, err);
     if (st != CCM_OK) return fail(st, err);
     DevMem part;
-    HIPCHK_API(part.alloc(size_t(kMaxGrid) * kScatterNV * 8, stream));
+    HIPCHK_API(part.alloc(size_t(kPartialsCap) * 8, stream));
     launch_scatter(og.g, int(d), kQ2, 0.0, nullptr, 0.0, nullptr, 1.0, Z, out, false, Payload{},
                    0.0, 0.0, nullptr, part.as<double>(), stream);
     HIPCHK_API(hipGetLastError());
@@ -275,7 +275,7 @@ ccm_status ccm_op_hess_matvec(const double* X, const double* U, int64_t n, int64
     if (repeats < 1) return fail(CCM_E_INVALID, "repeats >= 1");
     std::string err;
     OwnedGraph og;
-    st = graph_build(src, dst, w, m, n, true, stream, og, err);
+    st = graph_build(src, dst, w, m, n, int(d), true, stream, og, err);
     if (st != CCM_OK) return fail(st, err);
     const int64_t M = m * d;
     DevMem Pi, al, bi, cn, part;
@@ -283,7 +283,7 @@ ccm_status ccm_op_hess_matvec(const double* X, const double* U, int64_t n, int64
     HIPCHK_API(al.alloc(size_t(m) * 8, stream));
     HIPCHK_API(bi.alloc(size_t(m) * mask_words(int(d)) * 16, stream));
     HIPCHK_API(cn.alloc(size_t(m) * 4, stream));
-    HIPCHK_API(part.alloc(size_t(kMaxGrid) * 8 * 8, stream));
+    HIPCHK_API(part.alloc(size_t(kPartialsCap) * 8, stream));
     Payload pl{al.as<double>(), bi.as<uint64_t>(), cn.as<int>()};
     if (m > 0)
         launch_edge_ssnal(og.g, int(d), qk, gamma, sigma, X, U, Pi.as<double>(), pl,
@@ -318,15 +318,15 @@ ccm_status ccm_kkt(const double* A, const double* X, const double* U, int64_t n,
     if (!out_host) return fail(CCM_E_INVALID, "out_host is null");
     std::string err;
     OwnedGraph og;
-    st = graph_build(src, dst, w, m, n, true, stream, og, err);
+    st = graph_build(src, dst, w, m, n, int(d), true, stream, og, err);
     if (st != CCM_OK) return fail(st, err);
     const int64_t N = n * d, M = m * d;
     DevMem Uf, G, p1, p2, p3, sc;
     HIPCHK_API(Uf.alloc(size_t(M) * 8, stream));
     HIPCHK_API(G.alloc(size_t(N) * 8, stream));
-    HIPCHK_API(p1.alloc(size_t(kMaxGrid) * 8 * 8, stream));
-    HIPCHK_API(p2.alloc(size_t(kMaxGrid) * 8 * 8, stream));
-    HIPCHK_API(p3.alloc(size_t(kMaxGrid) * 8 * 8, stream));
+    HIPCHK_API(p1.alloc(size_t(kPartialsCap) * 8, stream));
+    HIPCHK_API(p2.alloc(size_t(kPartialsCap) * 8, stream));
+    HIPCHK_API(p3.alloc(size_t(kPartialsCap) * 8, stream));
     HIPCHK_API(sc.alloc(32 * 8, stream));
     double* s = sc.as<double>();
     // KKT edge pass on (X, U), writing Pi_C(U) for the dual objective

@@ -9,6 +9,8 @@ namespace ccm {
 constexpr int kBlock = 256;          // threads per workgroup for all row kernels
 constexpr int kWaves = kBlock / 64;  // waves per workgroup
 constexpr int kMaxGrid = 2048;       // cap on grid-stride grids (partials per kernel)
+// doubles in a partials buffer: two kernels of kMaxGrid blocks, up to 8 values each
+constexpr int kPartialsCap = 2 * kMaxGrid * 8;
 
 // q selector for the per-edge norm ||.||_q; the dual ball is in the q* norm.
 enum QKind : int { kQ1 = 1, kQ2 = 2, kQInf = 3 };

@@ -1,6 +1,8 @@
 // Device graph construction (see graph.hpp).
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+
 #include "graph.hpp"
 
 namespace ccm {
@@ -93,6 +95,45 @@ __global__ __launch_bounds__(kBlock) void k_inc_ptr(int64_t n, int64_t cnt,
         }
     }
     atomicMax(max_deg, best);
+}
+
+// first vertex of each chunk: the v with inc_ptr[v] <= c C < inc_ptr[v + 1]
+__global__ __launch_bounds__(kBlock) void k_chunk_v(int64_t n, int64_t nchunks, int C,
+                                                    const int* __restrict__ ptr,
+                                                    int* __restrict__ chunk_v) {
+    for (int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x; c < nchunks;
+         c += int64_t(gridDim.x) * kBlock) {
+        const int64_t p = c * C;
+        int64_t lo = 0, hi = n + 1;  // first index with ptr[idx] > p
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (ptr[mid] <= p) lo = mid + 1;
+            else hi = mid;
+        }
+        chunk_v[c] = int(lo - 1);
+    }
+}
+
+// vertices finished by the fix-up pass: isolated, or cut by a chunk boundary
+__global__ __launch_bounds__(kBlock) void k_special_flags(int64_t n, int C,
+                                                          const int* __restrict__ ptr,
+                                                          int* __restrict__ flag) {
+    for (int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x; v < n;
+         v += int64_t(gridDim.x) * kBlock) {
+        const int64_t b = ptr[v], e = ptr[v + 1];
+        flag[v] = (e == b) || (b / C != (e - 1) / C) ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_special_emit(int64_t n, const int* __restrict__ flag,
+                                                         const int* __restrict__ pos,
+                                                         int* __restrict__ special,
+                                                         int* __restrict__ count) {
+    for (int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x; v < n;
+         v += int64_t(gridDim.x) * kBlock) {
+        if (flag[v]) special[pos[v]] = int(v);
+        if (v == n - 1) count[0] = pos[v] + flag[v];
+    }
 }
 
 int bits_for(int64_t n) {
@@ -198,7 +239,8 @@ ccm_status graph_canonical_count(const int* src, const int* dst, const double* w
 }
 
 ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t m, int64_t n,
-                       bool require_canonical, hipStream_t s, OwnedGraph& out, std::string& err) {
+                       int d, bool require_canonical, hipStream_t s, OwnedGraph& out,
+                       std::string& err) {
     if (n < 1 || n > (int64_t(1) << 30) || m < 0 || m > (int64_t(1) << 30)) {
         err = "graph size out of range";
         return CCM_E_INVALID;
@@ -256,6 +298,40 @@ ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t 
     out.g.inc_ptr = out.inc_ptr.as<int>();
     out.g.inc = out.inc.as<Inc>();
     out.g.max_deg = md;
+    // balanced chunks of the incidence array and the fix-up vertex list
+    const int C = chunk_for(d);
+    const int64_t nch = (cnt + C - 1) / C;
+    out.g.chunk = C;
+    out.g.nchunks = nch;
+    HIPCHK(out.chunk_v.alloc(size_t(std::max<int64_t>(nch, 1)) * 4, s));
+    HIPCHK(out.special.alloc(size_t(n) * 4, s));
+    HIPCHK(out.carry.alloc(size_t(std::max<int64_t>(nch, 1)) * 2 * 2 * size_t(d) * 8, s));
+    if (nch > 0)
+        hipLaunchKernelGGL(k_chunk_v, dim3(flat_grid(nch)), dim3(kBlock), 0, s, n, nch, C,
+                           out.g.inc_ptr, out.chunk_v.as<int>());
+    {
+        DevMem flag, pos, temp2, count;
+        HIPCHK(flag.alloc(size_t(n) * 4, s));
+        HIPCHK(pos.alloc(size_t(n) * 4, s));
+        HIPCHK(count.alloc(4, s));
+        hipLaunchKernelGGL(k_special_flags, dim3(flat_grid(n)), dim3(kBlock), 0, s, n, C,
+                           out.g.inc_ptr, flag.as<int>());
+        size_t b = 0;
+        HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, b, flag.as<int>(), pos.as<int>(), int(n),
+                                                s));
+        HIPCHK(temp2.alloc(b, s));
+        HIPCHK(hipcub::DeviceScan::ExclusiveSum(temp2.p, b, flag.as<int>(), pos.as<int>(), int(n),
+                                                s));
+        hipLaunchKernelGGL(k_special_emit, dim3(flat_grid(n)), dim3(kBlock), 0, s, n,
+                           flag.as<int>(), pos.as<int>(), out.special.as<int>(), count.as<int>());
+        int ns = 0;
+        HIPCHK(hipMemcpyAsync(&ns, count.p, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        out.g.nspecial = ns;
+    }
+    out.g.chunk_v = out.chunk_v.as<int>();
+    out.g.special = out.special.as<int>();
+    out.g.carry = out.carry.as<double>();
     return CCM_OK;
 }
 

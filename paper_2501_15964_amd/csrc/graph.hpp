@@ -32,15 +32,17 @@ struct DevMem {
 
 struct OwnedGraph {
     DevGraph g;
-    DevMem src, dst, w, inc_ptr, inc;
+    DevMem src, dst, w, inc_ptr, inc, chunk_v, special, carry;
 };
 
-// Builds `out` from caller edges.  With require_canonical the edges must
-// already be canonical (src < dst, strictly increasing (src, dst), w > 0)
-// and are referenced in place; otherwise they are canonicalised into owned
-// arrays.  Returns CCM_OK or an error with text in `err`.  Synchronises s.
+// Builds `out` from caller edges for rows of d values.  With
+// require_canonical the edges must already be canonical (src < dst, strictly
+// increasing (src, dst), w > 0) and are referenced in place; otherwise they
+// are canonicalised into owned arrays.  Returns CCM_OK or an error with text
+// in `err`.  Synchronises s.
 ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t m, int64_t n,
-                       bool require_canonical, hipStream_t s, OwnedGraph& out, std::string& err);
+                       int d, bool require_canonical, hipStream_t s, OwnedGraph& out,
+                       std::string& err);
 
 // Number of canonical edges for the given input (synchronises s).
 ccm_status graph_canonical_count(const int* src, const int* dst, const double* w, int64_t m,

@@ -13,20 +13,20 @@ template <int V>
 using IC = std::integral_constant<int, V>;
 
 // Row layout: LPR lanes of a wave handle one row of d values, NPER values
-// per lane (coordinate k = lane_in_group + LPR * t).  Rows of up to 64
-// values use one value per lane; longer rows use the whole wave.
+// per lane (coordinate k = lane_in_group + LPR * t).  Up to 256 values a lane
+// holds at most 4, so a wave works on several rows at once and the per-row
+// reductions stay short; longer rows use the whole wave.
 inline bool row_supported(int64_t d) { return d >= 1 && d <= 1024; }
 
 template <class F>
 inline void dispatch_row(int d, F&& f) {
-    if (d <= 1) f(IC<1>{}, IC<1>{});
-    else if (d <= 2) f(IC<2>{}, IC<1>{});
-    else if (d <= 4) f(IC<4>{}, IC<1>{});
-    else if (d <= 8) f(IC<8>{}, IC<1>{});
-    else if (d <= 16) f(IC<16>{}, IC<1>{});
-    else if (d <= 32) f(IC<32>{}, IC<1>{});
-    else if (d <= 64) f(IC<64>{}, IC<1>{});
-    else if (d <= 128) f(IC<64>{}, IC<2>{});
+    if (d <= 2) f(IC<1>{}, IC<2>{});
+    else if (d <= 4) f(IC<1>{}, IC<4>{});
+    else if (d <= 8) f(IC<2>{}, IC<4>{});
+    else if (d <= 16) f(IC<4>{}, IC<4>{});
+    else if (d <= 32) f(IC<8>{}, IC<4>{});
+    else if (d <= 64) f(IC<16>{}, IC<4>{});
+    else if (d <= 128) f(IC<32>{}, IC<4>{});
     else if (d <= 256) f(IC<64>{}, IC<4>{});
     else if (d <= 512) f(IC<64>{}, IC<8>{});
     else f(IC<64>{}, IC<16>{});
@@ -54,10 +54,12 @@ inline int row_grid(int64_t rows, int lpr) {
     return int(g);
 }
 
+// grid of the element-wise kernels; kept small because the CG update
+// re-reduces the partial sums of the previous kernels in every block
 inline int flat_grid(int64_t count) {
     int64_t g = (count + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
-    if (g > kMaxGrid) g = kMaxGrid;
+    if (g > 1024) g = 1024;
     return int(g);
 }
 
@@ -83,7 +85,22 @@ struct DevGraph {
     const int* inc_ptr = nullptr;  // n + 1
     const Inc* inc = nullptr;      // 2 m
     int max_deg = 0;
+    // Balanced split of the incidence array for the vertex kernels: chunk c
+    // holds incidences [c C, (c + 1) C).  A vertex whose incidence range lies
+    // inside one chunk is finished by that chunk; a vertex cut by a chunk
+    // boundary leaves one partial row per chunk in `carry`, summed in chunk
+    // order by a fix-up pass that also handles isolated vertices.
+    int chunk = 16;                 // C
+    int64_t nchunks = 0;
+    const int* chunk_v = nullptr;   // vertex owning the first incidence of each chunk
+    const int* special = nullptr;   // vertices finished by the fix-up pass
+    int64_t nspecial = 0;
+    double* carry = nullptr;        // nchunks x 2 slots x (2 d) doubles
 };
+
+// incidences per chunk: about one typical vertex for long rows, several
+// short vertices for short rows
+inline int chunk_for(int d) { return d <= 64 ? 16 : d <= 256 ? 32 : 64; }
 
 // ---- edge kernels (edge_kernels.hip) --------------------------------------
 // SSNAL edge pass: Y = U + sigma B X, Pi = Pi_C(Y), payload; partials per

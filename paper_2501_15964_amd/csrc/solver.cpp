@@ -79,6 +79,11 @@ struct Prof {
         used += 2;
         open_cls = -1;
     }
+    // index of the most recent recorded pair (for reclassification)
+    int last_pair() const { return on && used >= 2 ? int(used / 2) - 1 : -1; }
+    void reclass(int pair, int c) {
+        if (on && pair >= 0 && size_t(pair) < used / 2) cls[pair] = c;
+    }
     // after a stream synchronisation: accumulate every recorded pair
     void harvest() {
         if (!on) return;
@@ -152,7 +157,9 @@ struct Solver::Impl {
     double sigma = 0;
     // ADMM state validity
     bool admm_state = false;
-    double last_bytes = 0;
+    double last_bytes = 0;      // algorithmic bytes of one Newton matvec at the current state
+    int64_t matvec_work = 0;    // matvec launches that did work (this gamma)
+    double matvec_bytes_sum = 0;
 
     Impl(const DevGraph& graph, int d_, int qk_, const double* A_, hipStream_t s_,
          const ccm_options& opt, double tol_, std::string& e)
@@ -201,7 +208,7 @@ struct Solver::Impl {
         HIPCHK(rank.alloc((n + 1) * 4, s));
         ltemp_bytes = labels_temp_bytes(n);
         HIPCHK(ltemp.alloc(ltemp_bytes, s));
-        const size_t pb = size_t(kMaxGrid) * 8 * 8;
+        const size_t pb = size_t(kPartialsCap) * 8;
         for (DevMem* b : {&pe, &pet, &ps, &pst, &pt, &pk, &pm, &pm2, &pupd0, &pupd1, &pwu0, &pwu1})
             HIPCHK(b->alloc(pb, s));
         HIPCHK(dsc.alloc(kNS * 8, s));
@@ -310,6 +317,10 @@ struct Solver::Impl {
         return v;
     }
 
+    double lap_bytes() const {
+        // ADMM matrix I + sigma B^T B: vectors and incidence lists only
+        return 16.0 * double(N) + 4.0 * double(n + 1) + 16.0 * double(m);
+    }
     double matvec_bytes(double nout) const {
         // one-pass minimum traffic of a Newton matvec launch: read V, write
         // out, incidence lists, and the per-edge payload (rows of Pi only for
@@ -338,27 +349,48 @@ struct Solver::Impl {
         int j = 0;
         hflag[0] = 0;
         hflag[1] = 0;
+        std::vector<int> mv_pair(chunk, -1), upd_pair(chunk, -1);
         while (j < o.cg_max_iter) {
+            const int j0 = j;
             for (int c = 0; c < chunk && j < o.cg_max_iter; ++c, ++j) {
                 {
                     Timed t(prof, CCM_K_CGUPDATE);
                     launch_cg_update(N, j, Dv, cg, thr, s);
                 }
-                Timed t(prof, CCM_K_MATVEC);
-                CgSkip sk;
-                sk.rr_partials = cg.upd[(j + 1) & 1];
-                sk.nparts = cg.nparts;
-                sk.thr = thr;
-                sk.done = cg.flag;
-                launch_matvec(g, d, qk, mode, cg.u, Pic, p, gamma, sigma, 1.0, nullptr, cg.w,
-                              cg.wu[(j + 1) & 1], sk, s);
+                upd_pair[c] = prof.last_pair();
+                {
+                    Timed t(prof, CCM_K_MATVEC);
+                    CgSkip sk;
+                    sk.rr_partials = cg.upd[(j + 1) & 1];
+                    sk.nparts = cg.nparts;
+                    sk.thr = thr;
+                    sk.done = cg.flag;
+                    launch_matvec(g, d, qk, mode, cg.u, Pic, p, gamma, sigma, 1.0, nullptr, cg.w,
+                                  cg.wu[(j + 1) & 1], sk, s);
+                }
+                mv_pair[c] = prof.last_pair();
             }
             HIPCHK(hipMemcpyAsync(hflag, cg.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
+            // launches issued after convergence return at once: time them as
+            // "other" so the matvec class holds only matvecs that did work
+            if (hflag[0]) {
+                const int done_at = hflag[1];
+                for (int c = 0; c < j - j0; ++c) {
+                    const int jj = j0 + c;
+                    if (jj >= done_at) prof.reclass(upd_pair[c], CCM_K_OTHER);
+                    if (jj + 1 >= done_at) prof.reclass(mv_pair[c], CCM_K_OTHER);
+                }
+            }
             prof.harvest();
             if (hflag[0]) break;
         }
         iters = hflag[0] ? hflag[1] : j;
+        // matvec launches that did work: the initial one plus one per
+        // iteration whose residual was still above the threshold
+        const int work = hflag[0] ? std::max(1, hflag[1]) : 1 + j;
+        matvec_work += work;
+        matvec_bytes_sum += double(work) * (mode == 0 ? last_bytes : lap_bytes());
         return CCM_OK;
     }
 
@@ -746,7 +778,10 @@ ccm_status Solver::run_path(const double* gammas, int T, const double* Xw, const
         st.f_p = res[4];
         st.f_d = res[5];
         st.sigma = I.sigma;
-        st.edge_bytes = I.last_bytes;
+        st.matvec_bytes = I.matvec_bytes_sum;
+        st.matvec_launches = I.matvec_work;
+        I.matvec_bytes_sum = 0;
+        I.matvec_work = 0;
         I.prof.take(st);
         if (stats) stats[t] = st;
     }

@@ -26,7 +26,7 @@ def test_header_symbols_exported():
 
 def test_struct_sizes():
     assert ctypes.sizeof(ccm.CcmOptions) == 64
-    assert ctypes.sizeof(ccm.CcmStats) == 136
+    assert ctypes.sizeof(ccm.CcmStats) == 144
     o = ccm.ccm_default_options()
     assert o.method == 0 and o.max_outer == 300 and o.cg_max_iter == 500
     assert ccm.ccm_version().startswith("libccm")
