@@ -175,6 +175,36 @@ ccm_status ccm_solve_path(const double* A, int64_t n, int64_t d,
                           ccm_stats* stats_host,
                           const double* X_warm, const double* U_warm, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Vector-Jacobian product of the solution map X*(A, w, gamma) at one gamma,
+ * q = 2 (implicit differentiation of the optimality conditions of (CCM),
+ * Section 1, through the generalized Jacobian of the SSNAL subproblem in its
+ * exact limit).  With the clusters c of a solution held fixed (every edge
+ * with a positive fusion margin), the points of a cluster share one value
+ * and the adjoint system in cluster space is
+ *     (diag(|c|) (x) I + B_c^T H B_c) lambda = g,   g_c = sum_{i in c} dL/dx_i,
+ *     H_l = gamma w_l (I - ghat ghat^T) / ||x_i - x_j||   (edges joining two clusters),
+ * solved by preconditioned CG; then
+ *     dL/da_i = lambda_{c(i)},
+ *     dL/dlog w_l = -gamma w_l <lambda_{c(i)} - lambda_{c(j)}, ghat_l>  (0 inside a cluster),
+ *     dL/dgamma = -sum_l w_l <lambda_{c(i)} - lambda_{c(j)}, ghat_l>.
+ *
+ * A, X, dL_dX, dL_dA : n x d (device).  X and labels must come from a tight
+ *                      solve at this gamma (e.g. ccm_solve_path with tol 1e-10).
+ * src, dst, w        : canonical edges (src < dst, sorted, w > 0), m of them.
+ * labels             : int32[n] cluster labels in [0, K) (ccm_solve_path output).
+ * dL_dlogw           : double[m] (device) or NULL;  dL_dgamma_host: double or NULL.
+ * tol, max_iter      : CG stop at ||residual|| <= tol ||g|| or max_iter iterations.
+ * iters_host         : CG iterations used (may be NULL).
+ * Errors: CCM_E_UNSUPPORTED for q != 2; CCM_E_INVALID (sizes, non-canonical
+ * edges, labels out of range).  Synchronises `stream`.
+ */
+ccm_status ccm_path_vjp(const double* A, int64_t n, int64_t d, const int32_t* src,
+                        const int32_t* dst, const double* w, int64_t m, double gamma, double q,
+                        const double* X, const int32_t* labels, const double* dL_dX,
+                        double* dL_dA, double* dL_dlogw, double* dL_dgamma_host, double tol,
+                        int32_t max_iter, int32_t* iters_host, hipStream_t stream);
+
 /* Number of canonical edges the library derives from (src, dst, w); the
  * row count of each U_out block.  Synchronises `stream`. */
 ccm_status ccm_canonical_edge_count(const int32_t* src, const int32_t* dst, const double* w,

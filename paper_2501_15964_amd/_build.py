@@ -27,7 +27,9 @@ SOURCES = [
     "labels.hip",
     "graph.hip",
     "knn.hip",
+    "adjoint.hip",
     "solver.cpp",
+    "vjp.cpp",
     "api.cpp",
 ]
 

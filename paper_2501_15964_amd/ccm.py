@@ -21,7 +21,7 @@ __all__ = [
     "ccm_version", "ccm_default_options", "ccm_build_knn_graph", "ccm_solve_path",
     "ccm_canonical_edge_count", "ccm_op_gather", "ccm_op_project", "ccm_op_prox",
     "ccm_op_scatter", "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy",
-    "EXPORTED_SYMBOLS",
+    "ccm_path_vjp", "CCMSolve", "EXPORTED_SYMBOLS",
 ]
 
 CCM_SSNAL, CCM_ADMM, CCM_AMA = 0, 1, 2
@@ -35,7 +35,7 @@ EXPORTED_SYMBOLS = [
     "ccm_status_string", "ccm_last_error", "ccm_version", "ccm_default_options",
     "ccm_build_knn_graph", "ccm_solve_path", "ccm_canonical_edge_count",
     "ccm_op_gather", "ccm_op_project", "ccm_op_prox", "ccm_op_scatter",
-    "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy",
+    "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy", "ccm_path_vjp",
 ]
 
 
@@ -108,6 +108,7 @@ def lib():
         "ccm_kkt": [P, P, P, I64, I64, P, P, P, I64, F64, F64, P, P],
         "ccm_labels": [P, P, I64, I64, P, P, I64, P, P, P],
         "ccm_stream_copy": [P, P, I64, I32, P, P],
+        "ccm_path_vjp": [P, I64, I64, P, P, P, I64, F64, F64, P, P, P, P, P, P, F64, I32, P, P],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -313,3 +314,66 @@ def ccm_stream_copy(src, dst, nbytes, repeats=1, stream=None):
     _check(lib().ccm_stream_copy(P(src.data_ptr()), P(dst.data_ptr()), int(nbytes), int(repeats),
                                  ctypes.byref(ms), _stream(stream)))
     return ms.value
+
+
+def ccm_path_vjp(A, src, dst, w, gamma, X, labels, dLdX, tol=1e-12, max_iter=5000, q=2.0,
+                 stream=None):
+    """VJP of X*(A, w, gamma) at one gamma (q = 2).  Returns (dL/dA, dL/dlog w,
+    dL/dgamma, CG iterations)."""
+    torch = _torch()
+    n, d = A.shape
+    m = src.numel()
+    dA = torch.empty_like(A)
+    dlw = torch.empty(max(m, 1), dtype=torch.float64, device=A.device)
+    dg = ctypes.c_double(0.0)
+    it = ctypes.c_int32(0)
+    _check(lib().ccm_path_vjp(_ptr(_f64(A)), n, d, _ptr(_i32(src)) if m else None,
+                              _ptr(_i32(dst)) if m else None, _ptr(_f64(w)) if m else None, m,
+                              float(gamma), float(q), _ptr(_f64(X)), _ptr(_i32(labels)),
+                              _ptr(_f64(dLdX.contiguous())), _ptr(dA), _ptr(dlw),
+                              ctypes.byref(dg), float(tol), int(max_iter), ctypes.byref(it),
+                              _stream(stream)))
+    return dA, dlw[:m], dg.value, it.value
+
+
+def _make_ccm_solve():
+    torch = _torch()
+
+    class CCMSolve(torch.autograd.Function):
+        """X = CCMSolve.apply(A, log_w, gamma, src, dst, tol): the minimiser of
+        (CCM) at one gamma with q = 2 and weights exp(log_w) on the canonical
+        edges (src, dst).  The forward pass runs ccm_solve_path to relative
+        KKT <= tol; the backward pass runs ccm_path_vjp.  Gradients flow to A,
+        log_w and gamma (a 0-d tensor)."""
+
+        @staticmethod
+        def forward(ctx, A, log_w, gamma, src, dst, tol=1e-11):
+            w = torch.exp(log_w).contiguous()
+            g = float(gamma)
+            out = ccm_solve_path(A.contiguous(), src, dst, w, [g], 2.0, tol)
+            X = out["X"][0]
+            labels = out["labels"][0]
+            ctx.save_for_backward(A, w, X, labels, src, dst)
+            ctx.gamma = g
+            return X
+
+        @staticmethod
+        def backward(ctx, gX):
+            A, w, X, labels, src, dst = ctx.saved_tensors
+            dA, dlw, dg, _ = ccm_path_vjp(A, src, dst, w, ctx.gamma, X, labels, gX)
+            gam = torch.tensor(dg, dtype=torch.float64, device=A.device)
+            return dA, dlw, gam, None, None, None
+
+    return CCMSolve
+
+
+class _LazySolve:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazySolve._cls is None:
+            _LazySolve._cls = _make_ccm_solve()
+        return getattr(_LazySolve._cls, name)
+
+
+CCMSolve = _LazySolve()

@@ -7,6 +7,7 @@
 
 #include "knn.hpp"
 #include "solver.hpp"
+#include "vjp.hpp"
 
 using namespace ccm;
 
@@ -191,6 +192,32 @@ ccm_status ccm_solve_path(const double* A, int64_t n, int64_t d, const int32_t* 
                          n_clusters_host, kkt_host, status_host, stats_host);
     if (st != CCM_OK) return fail(st, err);
     HIPCHK_API(hipStreamSynchronize(stream));
+    return CCM_OK;
+}
+
+ccm_status ccm_path_vjp(const double* A, int64_t n, int64_t d, const int32_t* src,
+                        const int32_t* dst, const double* w, int64_t m, double gamma, double q,
+                        const double* X, const int32_t* labels, const double* dL_dX,
+                        double* dL_dA, double* dL_dlogw, double* dL_dgamma_host, double tol,
+                        int32_t max_iter, int32_t* iters_host, hipStream_t stream) {
+    g_err.clear();
+    ccm_status st = check_dims(n, d);
+    if (st != CCM_OK) return st;
+    if (q != 2.0) return fail(CCM_E_UNSUPPORTED, "the adjoint is implemented for q = 2");
+    if (!A || !X || !labels || !dL_dX || !dL_dA) return fail(CCM_E_INVALID, "null argument");
+    if (m < 0 || (m > 0 && (!src || !dst || !w))) return fail(CCM_E_INVALID, "bad edges");
+    if (!(gamma >= 0) || !std::isfinite(gamma)) return fail(CCM_E_INVALID, "bad gamma");
+    if (!(tol > 0) || max_iter < 1) return fail(CCM_E_INVALID, "tol > 0, max_iter >= 1");
+    st = check_finite(X, n * d, stream, "X");
+    if (st != CCM_OK) return st;
+    st = check_finite(dL_dX, n * d, stream, "dL_dX");
+    if (st != CCM_OK) return st;
+    std::string err;
+    int it = 0;
+    st = path_vjp(A, n, int(d), src, dst, w, m, gamma, X, labels, dL_dX, dL_dA, dL_dlogw,
+                  dL_dgamma_host, tol, max_iter, &it, stream, err);
+    if (iters_host) *iters_host = it;
+    if (st != CCM_OK) return fail(st, err);
     return CCM_OK;
 }
 

@@ -225,6 +225,49 @@ ccm_status validate(const int* src, const int* dst, const double* w, int64_t m, 
 
 }  // namespace
 
+__global__ __launch_bounds__(kBlock) void k_member_entries(int64_t n, const int* __restrict__ labels,
+                                                           int* __restrict__ key,
+                                                           Inc* __restrict__ val) {
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * kBlock) {
+        key[i] = labels[i];
+        val[i] = Inc{int(i), 0};
+    }
+}
+
+ccm_status membership_build(const int* labels, int64_t n, int64_t K, int d, hipStream_t s,
+                            OwnedGraph& out, std::string& err) {
+    // rows: clusters; entries: member vertices in ascending order (a stable
+    // sort by label keeps vertex order inside each cluster)
+    DevMem key, key_s, val, temp, maxdeg;
+    HIPCHK(key.alloc(size_t(n) * 4, s));
+    HIPCHK(key_s.alloc(size_t(n) * 4, s));
+    HIPCHK(val.alloc(size_t(n) * 8, s));
+    HIPCHK(out.inc.alloc(size_t(n) * 8, s));
+    HIPCHK(out.inc_ptr.alloc(size_t(K + 1) * 4, s));
+    HIPCHK(maxdeg.alloc(4, s));
+    HIPCHK(hipMemsetAsync(maxdeg.p, 0, 4, s));
+    hipLaunchKernelGGL(k_member_entries, dim3(flat_grid(n)), dim3(kBlock), 0, s, n, labels,
+                       key.as<int>(), val.as<Inc>());
+    size_t b = 0;
+    const int nb = bits_for(K);
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, b, key.as<int>(), key_s.as<int>(),
+                                              val.as<unsigned long long>(),
+                                              out.inc.as<unsigned long long>(), int(n), 0, nb, s));
+    HIPCHK(temp.alloc(b, s));
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(temp.p, b, key.as<int>(), key_s.as<int>(),
+                                              val.as<unsigned long long>(),
+                                              out.inc.as<unsigned long long>(), int(n), 0, nb, s));
+    hipLaunchKernelGGL(k_inc_ptr, dim3(flat_grid(K + 1)), dim3(kBlock), 0, s, K, n,
+                       key_s.as<int>(), out.inc_ptr.as<int>(), maxdeg.as<int>());
+    out.g.n = K;
+    out.g.m = 0;
+    out.g.nent = n;
+    out.g.inc_ptr = out.inc_ptr.as<int>();
+    out.g.inc = out.inc.as<Inc>();
+    return build_chunks(d, s, out, err);
+}
+
 ccm_status graph_canonical_count(const int* src, const int* dst, const double* w, int64_t m,
                                  int64_t n, hipStream_t s, int64_t& m_canon, std::string& err) {
     bool canonical = true;
@@ -298,7 +341,14 @@ ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t 
     out.g.inc_ptr = out.inc_ptr.as<int>();
     out.g.inc = out.inc.as<Inc>();
     out.g.max_deg = md;
+    out.g.nent = cnt;
+    return build_chunks(d, s, out, err);
+}
+
+ccm_status build_chunks(int d, hipStream_t s, OwnedGraph& out, std::string& err) {
     // balanced chunks of the incidence array and the fix-up vertex list
+    const int64_t n = out.g.n;
+    const int64_t cnt = out.g.nent;
     const int C = chunk_for(d);
     const int64_t nch = (cnt + C - 1) / C;
     out.g.chunk = C;

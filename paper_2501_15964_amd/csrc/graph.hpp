@@ -44,6 +44,17 @@ ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t 
                        int d, bool require_canonical, hipStream_t s, OwnedGraph& out,
                        std::string& err);
 
+// Chunk decomposition (chunk_v, special, carry) of out.g's incidence lists
+// for rows of d values; needs out.g.n, nent, inc_ptr.  Synchronises s.
+ccm_status build_chunks(int d, hipStream_t s, OwnedGraph& out, std::string& err);
+
+// Cluster membership lists as a graph for the vertex kernels: row c lists
+// the vertices with labels == c (labels in [0, K)), entries {vertex, 0}.
+// With it, launch_scatter(cx = 0, cz = 1, Z = vertex rows) sums vertex rows
+// per cluster in vertex order.  Synchronises s.
+ccm_status membership_build(const int* labels, int64_t n, int64_t K, int d, hipStream_t s,
+                            OwnedGraph& out, std::string& err);
+
 // Number of canonical edges for the given input (synchronises s).
 ccm_status graph_canonical_count(const int* src, const int* dst, const double* w, int64_t m,
                                  int64_t n, hipStream_t s, int64_t& m_canon, std::string& err);

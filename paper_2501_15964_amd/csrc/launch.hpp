@@ -90,6 +90,7 @@ struct DevGraph {
     // inside one chunk is finished by that chunk; a vertex cut by a chunk
     // boundary leaves one partial row per chunk in `carry`, summed in chunk
     // order by a fix-up pass that also handles isolated vertices.
+    int64_t nent = 0;               // incidence entries (2 m for an edge graph)
     int chunk = 16;                 // C
     int64_t nchunks = 0;
     const int* chunk_v = nullptr;   // vertex owning the first incidence of each chunk
@@ -151,7 +152,9 @@ int launch_scatter(const DevGraph& g, int d, int qk, double cx, const double* X,
                    hipStream_t s);
 
 // Newton matvec: out = c0 V + sigma sum_{l ~ i} P_l (v_i - v_other) with the
-// SSNAL payload (mode 0) or P_l = I (mode 1, the ADMM matrix I + sigma B^T B).
+// SSNAL payload (mode 0), P_l = I (mode 1, the ADMM matrix I + sigma B^T B),
+// or P_l = a_l (I - yhat yhat^T) on every edge with a_l > 0 and 0 elsewhere
+// (mode 2, the adjoint curvature; q = 2 payload layout, no identity branch).
 // Optional per-vertex diagonal scale `dscale` (n values) replaces c0.
 // partials (1): <V, out>.  If rr_partials is non-null the kernel returns at
 // once when the CG residual recorded there is below thr or *done is set.
@@ -208,6 +211,27 @@ void launch_lap_dinv(const DevGraph& g, int d, double c0, double sigma, double* 
 void launch_spread(const double* A, int64_t n, int d, double* work, double* out, hipStream_t s);
 int spread_work_size(int64_t n, int d);
 void launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
+
+// ---- adjoint (adjoint.hip) ----------------------------------------------------
+// Per edge: delta = x_i - x_j; for an edge joining two clusters
+// alpha = gamma w / ||delta|| and Pi = gamma w delta / ||delta||, else alpha = 0.
+void launch_adj_payload(const DevGraph& g, int d, const double* X, const int* labels,
+                        double gamma, double* alpha, double* Pi, hipStream_t s);
+// v[i, :] = lam[labels[i], :]
+void launch_expand(int64_t n, int d, const int* labels, const double* lam, double* v,
+                   hipStream_t s);
+// dlogw_l = -gamma w_l <lam_ci - lam_cj, ghat_l> on inter-cluster edges (0
+// inside a cluster); partials (1): sum_l w_l <lam_ci - lam_cj, ghat_l>.
+int launch_adj_edge(const DevGraph& g, int d, const double* X, const int* labels,
+                    const double* lam, double gamma, double* dlogw, double* partials,
+                    hipStream_t s);
+// out[c] = 1 / (ptr[c + 1] - ptr[c])
+void launch_inv_sizes(int64_t K, const int* ptr, double* out, hipStream_t s);
+// range[0] = min label, range[1] = max label (range preset to INT_MAX, -1)
+void launch_label_range(int64_t n, const int* labels, int* range, hipStream_t s);
+// per-row scale: out[i, :] = x[i, :] * rs[i]
+void launch_rowscale(const double* x, const double* rs, double* out, int64_t rows, int d,
+                     hipStream_t s);
 
 // ---- labels (labels.hip) --------------------------------------------------
 // labels from fused flags: connected components, numbered by smallest vertex.

@@ -39,7 +39,7 @@ struct Meta {
     int cnt;
 };
 
-template <int Q, bool PAY>
+template <int Q, bool PAY, bool ADJ = false>
 __device__ __forceinline__ Meta load_meta(const Inc* __restrict__ inc, int64_t p,
                                           const Payload& pl, const double* __restrict__ w,
                                           double gamma) {
@@ -54,7 +54,7 @@ __device__ __forceinline__ Meta load_meta(const Inc* __restrict__ inc, int64_t p
     m.cnt = -1;
     if constexpr (PAY && Q == kQ2) {
         m.a = pl.alpha[m.l];
-        if (m.a < 1.0 && m.a > 0.0) {
+        if ((ADJ || m.a < 1.0) && m.a > 0.0) {
             const double r = gamma * w[m.l];
             m.ir = 1.0 / r;
             m.f = m.a * m.ir * m.ir;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_chunk(DevGraph g, int d, Sca
     const int gl = (threadIdx.x & 63) % LPR;
     constexpr int GPB = kBlock / LPR;
     const int W = (d + LPR - 1) / LPR;
-    const int64_t T = 2 * g.m;
+    const int64_t T = g.nent;
     const int C = g.chunk;
     const int CW = 2 * d;
     double acc4[kScatterNV] = {0.0, 0.0, 0.0, 0.0};
@@ -249,18 +249,19 @@ __device__ __forceinline__ void matvec_range(int64_t pa, int64_t pb, int d, int 
                                              const double* __restrict__ w, double gamma,
                                              const double (&vi)[NPER], double (&acc)[NPER]) {
     constexpr int U = Unroll<NPER>::U;
-    constexpr bool PAY = MODE == 0;
+    constexpr bool PAY = MODE == 0 || MODE == 2;
+    constexpr int QP = MODE == 2 ? kQ2 : Q;
     for (int64_t p0 = pa; p0 < pb; p0 += U) {
         Meta mt[U];
         double vo[U][NPER];
         double pv[U][NPER];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (p0 + u < pb) mt[u] = load_meta<Q, PAY>(inc, p0 + u, pl, w, gamma);
+            if (p0 + u < pb) mt[u] = load_meta<QP, PAY, MODE == 2>(inc, p0 + u, pl, w, gamma);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool ok = p0 + u < pb;
-            const bool rows = ok && PAY && Q == kQ2 && mt[u].f != 0.0;
+            const bool rows = ok && PAY && QP == kQ2 && mt[u].f != 0.0;
 #pragma unroll
             for (int t = 0; t < NPER; ++t) {
                 const int k = gl + LPR * t;
@@ -278,6 +279,16 @@ __device__ __forceinline__ void matvec_range(int64_t pa, int64_t pb, int d, int 
             if constexpr (MODE == 1) {
 #pragma unroll
                 for (int t = 0; t < NPER; ++t) acc[t] += dl[t];
+            } else if constexpr (MODE == 2) {
+                // adjoint curvature a (I - yhat yhat^T) on every edge with a > 0
+                if (m.a > 0.0) {
+                    double c = 0.0;
+#pragma unroll
+                    for (int t = 0; t < NPER; ++t) c += pv[u][t] * dl[t];
+                    c = group_sum<LPR>(c) * m.f;
+#pragma unroll
+                    for (int t = 0; t < NPER; ++t) acc[t] += m.a * dl[t] - c * pv[u][t];
+                }
             } else if constexpr (Q == kQ2) {
                 // P = I inside the ball; a (I - yhat yhat^T) outside with
                 // yhat = Pi_l / r, applied as a dl - (a / r^2) <Pi_l, dl> Pi_l
@@ -373,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec_chunk(DevGraph g, int d,
     const int gl = (threadIdx.x & 63) % LPR;
     constexpr int GPB = kBlock / LPR;
     const int W = (d + LPR - 1) / LPR;
-    const int64_t T = 2 * g.m;
+    const int64_t T = g.nent;
     const int C = g.chunk;
     const int CW = 2 * d;
     double dot[1] = {0.0};
@@ -493,6 +504,9 @@ int launch_matvec(const DevGraph& g, int d, int qk, int mode, const double* V, c
         if (g1 > 0) {
             if (mode == 1) {
                 hipLaunchKernelGGL((k_matvec_chunk<lpr, nper, kQ2, 1>), dim3(g1), dim3(kBlock), 0,
+                                   s, g, d, V, Pi, pl, gamma, mo, partials, skip);
+            } else if (mode == 2) {
+                hipLaunchKernelGGL((k_matvec_chunk<lpr, nper, kQ2, 2>), dim3(g1), dim3(kBlock), 0,
                                    s, g, d, V, Pi, pl, gamma, mo, partials, skip);
             } else {
                 dispatch_q(qk, [&](auto Qc) {

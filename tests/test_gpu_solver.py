@@ -152,3 +152,92 @@ def test_max_iter_status_and_time_budget():
     o = ccm.ccm_default_options(time_budget_s=1e-9)
     out = ccm.ccm_solve_path(dev(A), *graph_dev(src, dst, w), [0.3, 0.6], 2.0, 1e-12, opts=o)
     assert out["status"][0] == 2
+
+
+def _adjoint_problem(n_per=40, d=4, seed=1005):
+    A, _, T = synthdata.mixture32(seed=seed, n_per=n_per, d=d, n_blobs=4)
+    A = A / 3.0
+    src, dst, w, *_ = oracle.knn_graph(A, 5, None)
+    return A, src, dst, w, T
+
+
+def test_vjp_matches_oracle_gradient():
+    torch, ccm = need_gpu()
+    A, src, dst, w, T = _adjoint_problem()
+    n = A.shape[0]
+    S = oracle.fusion_scale(A)
+    # a gamma with partial fusion and clear margins
+    for g in (0.08, 0.15, 0.3):
+        Xo, Uo, _, info = oracle.ssnal(A, src, dst, w, g, 2.0, 1e-12)
+        lab, K = oracle.cluster_labels(Xo, src, dst, n, S)
+        mg = oracle.fusion_margins(Xo, Uo, src, dst, w, g, 2.0, S)
+        if 1 < K < n and mg.min() > 1e-3:
+            break
+    out = ccm.ccm_solve_path(dev(A), *graph_dev(src, dst, w), [g], 2.0, 1e-11)
+    X = out["X"][0]
+    assert np.array_equal(host(out["labels"][0]), lab)
+    G = 2 * (host(X) - T)
+    dA, dlw, dg, it = ccm.ccm_path_vjp(dev(A), *graph_dev(src, dst, w), g, X, out["labels"][0],
+                                       dev(G), tol=1e-13)
+    rA, rlw, rg = oracle.path_vjp(A, src, dst, w, g, Xo, 2 * (Xo - T), labels=lab)
+    assert rel(host(dA), rA) <= 1e-6
+    assert rel(host(dlw), rlw) <= 1e-6
+    assert abs(dg - rg) <= 1e-6 * (1 + abs(rg))
+
+
+def test_vjp_central_differences_on_gpu():
+    torch, ccm = need_gpu()
+    A, src, dst, w, T = _adjoint_problem(n_per=30, d=3, seed=77)
+    g = 0.12
+    sd = graph_dev(src, dst, w)
+
+    def solve(Ah, wh, gh):
+        o = ccm.ccm_solve_path(dev(Ah), sd[0], sd[1], dev(wh), [gh], 2.0, 1e-12)
+        return host(o["X"][0]), host(o["labels"][0])
+
+    X0, lab0 = solve(A, w, g)
+    loss = lambda X: float(((X - T) ** 2).sum())
+    out = ccm.ccm_solve_path(dev(A), *sd, [g], 2.0, 1e-12)
+    dA, dlw, dg, _ = ccm.ccm_path_vjp(dev(A), *sd, g, out["X"][0], out["labels"][0],
+                                      dev(2 * (X0 - T)), tol=1e-13)
+    dA, dlw = host(dA), host(dlw)
+    rng = np.random.default_rng(3)
+    h = 1e-6
+    checked = 0
+    for _ in range(4):
+        V = rng.normal(size=A.shape)
+        Xp, lp = solve(A + h * V, w, g)
+        Xm, lm = solve(A - h * V, w, g)
+        if not (np.array_equal(lp, lab0) and np.array_equal(lm, lab0)):
+            continue
+        fd = (loss(Xp) - loss(Xm)) / (2 * h)
+        assert abs(fd - float((dA * V).sum())) <= 1e-5 * (1 + abs(fd))
+        checked += 1
+    v = rng.normal(size=w.shape)
+    Xp, _ = solve(A, w * np.exp(h * v), g)
+    Xm, _ = solve(A, w * np.exp(-h * v), g)
+    fd = (loss(Xp) - loss(Xm)) / (2 * h)
+    assert abs(fd - float((dlw * v).sum())) <= 1e-5 * (1 + abs(fd))
+    Xp, _ = solve(A, w, g + h)
+    Xm, _ = solve(A, w, g - h)
+    fd = (loss(Xp) - loss(Xm)) / (2 * h)
+    assert abs(fd - dg) <= 1e-5 * (1 + abs(fd))
+    assert checked >= 2
+
+
+def test_ccmsolve_autograd():
+    torch, ccm = need_gpu()
+    A, src, dst, w, T = _adjoint_problem(n_per=20, d=3, seed=5)
+    At = dev(A).requires_grad_(True)
+    lw = dev(np.log(w)).requires_grad_(True)
+    gam = torch.tensor(0.1, dtype=torch.float64, device="cuda", requires_grad=True)
+    s, d_, _ = graph_dev(src, dst, w)
+    X = ccm.CCMSolve.apply(At, lw, gam, s, d_)
+    L = ((X - dev(T)) ** 2).sum()
+    L.backward()
+    out = ccm.ccm_solve_path(dev(A), *graph_dev(src, dst, w), [0.1], 2.0, 1e-11)
+    dA, dlw, dg, _ = ccm.ccm_path_vjp(dev(A), *graph_dev(src, dst, w), 0.1, out["X"][0],
+                                      out["labels"][0], 2 * (out["X"][0] - dev(T)))
+    assert torch.allclose(At.grad, dA, rtol=1e-8, atol=1e-10)
+    assert torch.allclose(lw.grad, dlw, rtol=1e-8, atol=1e-10)
+    assert abs(float(gam.grad) - dg) <= 1e-8 * (1 + abs(dg))
