@@ -176,6 +176,44 @@ ccm_status ccm_solve_path(const double* A, int64_t n, int64_t d,
                           const double* X_warm, const double* U_warm, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Batched paths: many independent (CCM) instances of uneven n, d and q, each
+ * solved along the same gamma sequence to its own relative KKT <= tol (its
+ * residuals normalised by its own norms).  Instances with equal (q, d) are
+ * solved together as one block-diagonal problem, so every kernel launch
+ * serves all of them; SSNAL only (opts->method is ignored).
+ *
+ * Instance i is described by inst_host[i]:
+ *   n, d, m   : points, features, edges (n >= 1, 1 <= d <= 1024, m >= 0);
+ *   a_offset  : element offset of its A (n x d, row-major) in A_all;
+ *   e_offset  : offset of its m edges in src_all / dst_all / w_all; endpoints
+ *               are local (0 .. n-1) and the edges canonical (src < dst,
+ *               sorted by (src, dst), w > 0);
+ *   x_offset  : element offset of its outputs in X_out_all: n_gamma
+ *               consecutive n x d blocks, gamma-major;
+ *   l_offset  : element offset in labels_all: n_gamma blocks of n labels
+ *               (numbered within the instance as in ccm_solve_path);
+ *   q         : 1.0, 2.0 or INFINITY.
+ * Host outputs are indexed [i * n_gamma + t]: n_clusters_host, status_host,
+ * and kkt_host (4 doubles each: R_D, R_C, R_U, eta).  labels_all, kkt_host,
+ * n_clusters_host and status_host may be NULL.
+ * Errors: CCM_E_INVALID (descriptor, edges), CCM_E_UNSUPPORTED (q, d).
+ * Synchronises `stream`.
+ */
+typedef struct {
+    int64_t n, d, m;
+    int64_t a_offset, e_offset, x_offset, l_offset;
+    double q;
+} ccm_instance;
+
+ccm_status ccm_solve_path_batched(const ccm_instance* inst_host, int32_t n_inst,
+                                  const double* A_all, const int32_t* src_all,
+                                  const int32_t* dst_all, const double* w_all,
+                                  const double* gammas_host, int32_t n_gamma, double tol,
+                                  const ccm_options* opts, double* X_out_all, int32_t* labels_all,
+                                  int32_t* n_clusters_host, double* kkt_host,
+                                  int32_t* status_host, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Vector-Jacobian product of the solution map X*(A, w, gamma) at one gamma,
  * q = 2 (implicit differentiation of the optimality conditions of (CCM),
  * Section 1, through the generalized Jacobian of the SSNAL subproblem in its

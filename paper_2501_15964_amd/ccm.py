@@ -21,7 +21,7 @@ __all__ = [
     "ccm_version", "ccm_default_options", "ccm_build_knn_graph", "ccm_solve_path",
     "ccm_canonical_edge_count", "ccm_op_gather", "ccm_op_project", "ccm_op_prox",
     "ccm_op_scatter", "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy",
-    "ccm_path_vjp", "CCMSolve", "EXPORTED_SYMBOLS",
+    "ccm_path_vjp", "CCMSolve", "ccm_solve_path_batched", "CcmInstance", "EXPORTED_SYMBOLS",
 ]
 
 CCM_SSNAL, CCM_ADMM, CCM_AMA = 0, 1, 2
@@ -36,6 +36,7 @@ EXPORTED_SYMBOLS = [
     "ccm_build_knn_graph", "ccm_solve_path", "ccm_canonical_edge_count",
     "ccm_op_gather", "ccm_op_project", "ccm_op_prox", "ccm_op_scatter",
     "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy", "ccm_path_vjp",
+    "ccm_solve_path_batched",
 ]
 
 
@@ -74,6 +75,14 @@ class CcmStats(ctypes.Structure):
                     matvec_launches=self.matvec_launches)
 
 
+class CcmInstance(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("d", ctypes.c_int64), ("m", ctypes.c_int64),
+        ("a_offset", ctypes.c_int64), ("e_offset", ctypes.c_int64),
+        ("x_offset", ctypes.c_int64), ("l_offset", ctypes.c_int64), ("q", ctypes.c_double),
+    ]
+
+
 _lib = None
 P = ctypes.c_void_p
 I64 = ctypes.c_int64
@@ -109,6 +118,7 @@ def lib():
         "ccm_labels": [P, P, I64, I64, P, P, I64, P, P, P],
         "ccm_stream_copy": [P, P, I64, I32, P, P],
         "ccm_path_vjp": [P, I64, I64, P, P, P, I64, F64, F64, P, P, P, P, P, P, F64, I32, P, P],
+        "ccm_solve_path_batched": [P, I32, P, P, P, P, P, I32, F64, P, P, P, P, P, P, P],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -377,3 +387,55 @@ class _LazySolve:
 
 
 CCMSolve = _LazySolve()
+
+
+def ccm_solve_path_batched(instances, gammas, tol, opts=None, stream=None):
+    """Solve many independent instances along the same gamma sequence.
+    instances: list of dicts with device tensors A (n x d float64), src, dst
+    (int32, canonical, local endpoints), w (float64) and a float q.  Returns a
+    list of dicts (one per instance) with X [T, n, d], labels [T, n],
+    n_clusters [T], kkt [T, 4], status [T]."""
+    torch = _torch()
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+    T = int(g.size)
+    N = len(instances)
+    desc = (CcmInstance * max(N, 1))()
+    a_off = e_off = x_off = l_off = 0
+    for i, inst in enumerate(instances):
+        n, d = inst["A"].shape
+        m = int(inst["src"].numel())
+        desc[i] = CcmInstance(n, d, m, a_off, e_off, x_off, l_off, float(inst["q"]))
+        a_off += n * d
+        e_off += m
+        x_off += T * n * d
+        l_off += T * n
+    dev = instances[0]["A"].device
+    A_all = torch.cat([inst["A"].reshape(-1) for inst in instances]).contiguous()
+    if e_off:
+        src_all = torch.cat([inst["src"] for inst in instances]).contiguous()
+        dst_all = torch.cat([inst["dst"] for inst in instances]).contiguous()
+        w_all = torch.cat([inst["w"] for inst in instances]).contiguous()
+    else:
+        src_all = dst_all = torch.zeros(1, dtype=torch.int32, device=dev)
+        w_all = torch.zeros(1, dtype=torch.float64, device=dev)
+    X_all = torch.empty(max(x_off, 1), dtype=torch.float64, device=dev)
+    L_all = torch.empty(max(l_off, 1), dtype=torch.int32, device=dev)
+    ncl = np.zeros(N * T, dtype=np.int32)
+    kkt = np.zeros(N * T * 4, dtype=np.float64)
+    st = np.zeros(N * T, dtype=np.int32)
+    o = opts if opts is not None else lib().ccm_default_options()
+    _check(lib().ccm_solve_path_batched(
+        ctypes.cast(desc, P), N, _ptr(A_all), _ptr(src_all), _ptr(dst_all), _ptr(w_all),
+        g.ctypes.data_as(P), T, float(tol), ctypes.byref(o), _ptr(X_all), _ptr(L_all),
+        ncl.ctypes.data_as(P), kkt.ctypes.data_as(P), st.ctypes.data_as(P), _stream(stream)))
+    out = []
+    for i, inst in enumerate(instances):
+        n, d = inst["A"].shape
+        D = desc[i]
+        out.append(dict(
+            X=X_all[D.x_offset:D.x_offset + T * n * d].view(T, n, d),
+            labels=L_all[D.l_offset:D.l_offset + T * n].view(T, n),
+            n_clusters=ncl[i * T:(i + 1) * T].copy(),
+            kkt=kkt[i * T * 4:(i + 1) * T * 4].reshape(T, 4).copy(),
+            status=st[i * T:(i + 1) * T].copy()))
+    return out

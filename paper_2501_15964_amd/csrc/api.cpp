@@ -1,6 +1,7 @@
 // C ABI entry points of libccm (declared in include/ccm.h): argument checks,
 // error reporting and dispatch to the device graph, solvers and kernels.
 #include <cmath>
+#include <map>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -191,6 +192,119 @@ ccm_status ccm_solve_path(const double* A, int64_t n, int64_t d, const int32_t* 
     st = solver.run_path(gammas_host, n_gamma, X_warm, U_warm, X_out, U_out, labels_out,
                          n_clusters_host, kkt_host, status_host, stats_host);
     if (st != CCM_OK) return fail(st, err);
+    HIPCHK_API(hipStreamSynchronize(stream));
+    return CCM_OK;
+}
+
+ccm_status ccm_solve_path_batched(const ccm_instance* inst_host, int32_t n_inst,
+                                  const double* A_all, const int32_t* src_all,
+                                  const int32_t* dst_all, const double* w_all,
+                                  const double* gammas_host, int32_t n_gamma, double tol,
+                                  const ccm_options* opts, double* X_out_all, int32_t* labels_all,
+                                  int32_t* n_clusters_host, double* kkt_host,
+                                  int32_t* status_host, hipStream_t stream) {
+    g_err.clear();
+    if (n_inst < 0 || (n_inst > 0 && !inst_host)) return fail(CCM_E_INVALID, "bad instances");
+    if (!A_all || !X_out_all) return fail(CCM_E_INVALID, "null A_all or X_out_all");
+    if (n_gamma < 0 || (n_gamma > 0 && !gammas_host))
+        return fail(CCM_E_INVALID, "bad gamma list");
+    for (int t = 0; t < n_gamma; ++t)
+        if (!std::isfinite(gammas_host[t]) || gammas_host[t] < 0)
+            return fail(CCM_E_INVALID, "gamma values must be finite and >= 0");
+    if (!(tol > 0) || !std::isfinite(tol)) return fail(CCM_E_INVALID, "tol must be > 0");
+    ccm_options o = opts ? *opts : defaults();
+    o.method = CCM_SSNAL;
+    if (o.max_outer < 1 || o.max_newton < 1 || o.cg_max_iter < 1)
+        return fail(CCM_E_INVALID, "iteration limits must be >= 1");
+    if (o.sigma0 <= 0) o.sigma0 = 10.0;
+    if (!(o.sigma_max >= o.sigma0)) o.sigma_max = o.sigma0;
+    // group instances by (q, d)
+    std::map<std::pair<int, int64_t>, std::vector<int>> groups;
+    for (int i = 0; i < n_inst; ++i) {
+        const ccm_instance& I = inst_host[i];
+        ccm_status st = check_dims(I.n, I.d);
+        if (st != CCM_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
+        int qk = 0;
+        if (!q_kind(I.q, qk))
+            return fail(CCM_E_UNSUPPORTED, "instance " + std::to_string(i) + ": q must be 1, 2 or inf");
+        if (I.m < 0 || I.a_offset < 0 || I.e_offset < 0 || I.x_offset < 0 || I.l_offset < 0)
+            return fail(CCM_E_INVALID, "instance " + std::to_string(i) + ": negative size/offset");
+        if (I.m > 0 && (!src_all || !dst_all || !w_all))
+            return fail(CCM_E_INVALID, "null edge arrays");
+        groups[{qk, I.d}].push_back(i);
+    }
+    if (n_gamma == 0) return CCM_OK;
+    for (auto& kv : groups) {
+        const int qk = kv.first.first;
+        const int d = int(kv.first.second);
+        const std::vector<int>& ids = kv.second;
+        const int S = int(ids.size());
+        BatchSpec b;
+        b.S = S;
+        b.vseg.assign(S + 1, 0);
+        b.eseg.assign(S + 1, 0);
+        std::vector<int64_t> xoff(S), loff(S);
+        for (int k = 0; k < S; ++k) {
+            const ccm_instance& I = inst_host[ids[k]];
+            b.vseg[k + 1] = b.vseg[k] + I.n;
+            b.eseg[k + 1] = b.eseg[k] + I.m;
+            xoff[k] = I.x_offset;
+            loff[k] = I.l_offset;
+        }
+        const int64_t nU = b.vseg[S], mU = b.eseg[S];
+        if (nU > (int64_t(1) << 30) || mU > (int64_t(1) << 30))
+            return fail(CCM_E_INVALID, "batched group too large");
+        DevMem Au, su, du, wu, seg, bad;
+        HIPCHK_API(Au.alloc(size_t(nU) * d * 8, stream));
+        HIPCHK_API(su.alloc(size_t(std::max<int64_t>(mU, 1)) * 4, stream));
+        HIPCHK_API(du.alloc(size_t(std::max<int64_t>(mU, 1)) * 4, stream));
+        HIPCHK_API(wu.alloc(size_t(std::max<int64_t>(mU, 1)) * 8, stream));
+        HIPCHK_API(seg.alloc(size_t(4 * S + 2) * 8, stream));
+        HIPCHK_API(bad.alloc(4, stream));
+        HIPCHK_API(hipMemsetAsync(bad.p, 0, 4, stream));
+        for (int k = 0; k < S; ++k) {
+            const ccm_instance& I = inst_host[ids[k]];
+            HIPCHK_API(hipMemcpyAsync(Au.as<double>() + b.vseg[k] * d, A_all + I.a_offset,
+                                      size_t(I.n) * d * 8, hipMemcpyDeviceToDevice, stream));
+            launch_offset_edges(I.m, src_all + I.e_offset, dst_all + I.e_offset,
+                                w_all + I.e_offset, int(b.vseg[k]), int(I.n),
+                                su.as<int>() + b.eseg[k], du.as<int>() + b.eseg[k],
+                                wu.as<double>() + b.eseg[k], bad.as<int>(), stream);
+        }
+        int64_t* sd = seg.as<int64_t>();
+        HIPCHK_API(hipMemcpyAsync(sd, b.vseg.data(), size_t(S + 1) * 8, hipMemcpyHostToDevice,
+                                  stream));
+        HIPCHK_API(hipMemcpyAsync(sd + (S + 1), b.eseg.data(), size_t(S + 1) * 8,
+                                  hipMemcpyHostToDevice, stream));
+        HIPCHK_API(hipMemcpyAsync(sd + 2 * (S + 1), xoff.data(), size_t(S) * 8,
+                                  hipMemcpyHostToDevice, stream));
+        HIPCHK_API(hipMemcpyAsync(sd + 2 * (S + 1) + S, loff.data(), size_t(S) * 8,
+                                  hipMemcpyHostToDevice, stream));
+        int hbad = 0;
+        HIPCHK_API(hipMemcpyAsync(&hbad, bad.p, 4, hipMemcpyDeviceToHost, stream));
+        HIPCHK_API(hipStreamSynchronize(stream));
+        if (hbad) return fail(CCM_E_INVALID, "instance edges must be canonical with local endpoints");
+        ccm_status st = check_finite(Au.as<double>(), nU * d, stream, "A");
+        if (st != CCM_OK) return st;
+        b.vseg_dev = sd;
+        b.eseg_dev = sd + (S + 1);
+        b.xoff_dev = sd + 2 * (S + 1);
+        b.loff_dev = sd + 2 * (S + 1) + S;
+        b.inst = ids;
+        b.X_out_all = X_out_all;
+        b.labels_all = labels_all;
+        b.n_clusters_host = n_clusters_host;
+        b.kkt_host = kkt_host;
+        b.status_host = status_host;
+        std::string err;
+        OwnedGraph og;
+        st = graph_build(su.as<int>(), du.as<int>(), wu.as<double>(), mU, nU, d, true, stream, og,
+                         err);
+        if (st != CCM_OK) return fail(st, err);
+        Solver solver(og.g, d, qk, Au.as<double>(), stream, o, tol, err);
+        st = solver.run_batched(gammas_host, n_gamma, b);
+        if (st != CCM_OK) return fail(st, err);
+    }
     HIPCHK_API(hipStreamSynchronize(stream));
     return CCM_OK;
 }

@@ -94,6 +94,16 @@ __device__ __forceinline__ void project_row(const double (&y)[NPER], int gl, int
                 s2 = group_sum<LPR>(s2);
                 c2 = group_sum_i<LPR>(c2);
                 if (c2 == cc) break;
+                if (c2 == 0) {
+                    // r is below the rounding resolution of max |y_k|: the
+                    // projection rounds to 0 (theta = max |y_k|, P = 0)
+                    double vm = 0.0;
+#pragma unroll
+                    for (int t = 0; t < NPER; ++t) vm = fmax(vm, v[t]);
+                    theta = group_max<LPR>(vm);
+                    cc = 0;
+                    break;
+                }
                 cc = c2;
                 theta = (s2 - r) / double(c2);
             }
@@ -192,7 +202,8 @@ __global__ __launch_bounds__(kBlock) void k_edge_kkt(int64_t m, int d, const int
                                                      const double* __restrict__ X,
                                                      const double* __restrict__ U,
                                                      double* __restrict__ Ufeas,
-                                                     double* __restrict__ partials) {
+                                                     double* __restrict__ partials,
+                                                     double* __restrict__ rowstats) {
     const int lane = threadIdx.x & 63;
     const int gl = lane % LPR;
     constexpr int GPB = kBlock / LPR;
@@ -218,30 +229,43 @@ __global__ __launch_bounds__(kBlock) void k_edge_kkt(int64_t m, int d, const int
             else if constexpr (Q == kQ2) nq += bx[t] * bx[t];
             else nq = fmax(nq, fabs(bx[t]));
         }
+        double pen = 0.0;  // r ||(BX)_l||_q, counted once per edge
         if constexpr (Q == kQ2) {
             nq = group_sum<LPR>(nq);
-            if (gl == 0) acc[4] += r * sqrt(nq);
+            pen = r * sqrt(nq);
         } else if constexpr (Q == kQInf) {
             nq = group_max<LPR>(nq);
-            if (gl == 0) acc[4] += r * nq;
+            pen = r * nq;
         } else {
-            acc[4] += r * nq;
+            pen = group_sum<LPR>(r * nq);
         }
+        if (gl == 0) acc[4] += pen;
         RowProj<LPR, NPER, Q> pv, pu;
         project_row<LPR, NPER, Q, false>(v, gl, lane, d, r, pv);
         project_row<LPR, NPER, Q, false>(u, gl, lane, d, r, pu);
+        double r4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int t = 0; t < NPER; ++t) {
             const int k = gl + LPR * t;
             if (k < d) {
                 const double e = pv.pi[t] - u[t];
                 const double f = u[t] - pu.pi[t];
-                acc[0] += e * e;
-                acc[1] += bx[t] * bx[t];
-                acc[2] += u[t] * u[t];
-                acc[3] += f * f;
+                r4[0] += e * e;
+                r4[1] += bx[t] * bx[t];
+                r4[2] += u[t] * u[t];
+                r4[3] += f * f;
                 if (Ufeas) Ufeas[l * d + k] = pu.pi[t];
             }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] += r4[c];
+        if (rowstats) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double tot = group_sum<LPR>(r4[c]);
+                if (gl == 0) rowstats[l * 5 + c] = tot;
+            }
+            if (gl == 0) rowstats[l * 5 + 4] = pen;
         }
     }
     block_reduce_store<kEdgeKktNV>(acc, partials + blockIdx.x * kEdgeKktNV);
@@ -446,7 +470,8 @@ int launch_edge_ssnal(const DevGraph& g, int d, int qk, double gamma, double sig
 }
 
 int launch_edge_kkt(const DevGraph& g, int d, int qk, double gamma, const double* X,
-                    const double* U, double* Ufeas, double* partials, hipStream_t s) {
+                    const double* U, double* Ufeas, double* partials, hipStream_t s,
+                    double* rowstats) {
     int grid = 1;
     dispatch_row(d, [&](auto L, auto N) {
         constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
@@ -454,7 +479,7 @@ int launch_edge_kkt(const DevGraph& g, int d, int qk, double gamma, const double
         dispatch_q(qk, [&](auto Qc) {
             constexpr int q = decltype(Qc)::value;
             hipLaunchKernelGGL((k_edge_kkt<lpr, nper, q>), dim3(grid), dim3(kBlock), 0, s, g.m, d,
-                               g.src, g.dst, g.w, gamma, X, U, Ufeas, partials);
+                               g.src, g.dst, g.w, gamma, X, U, Ufeas, partials, rowstats);
         });
     });
     return grid;

@@ -114,10 +114,11 @@ int launch_edge_ssnal(const DevGraph& g, int d, int qk, double gamma, double sig
 
 // KKT edge pass for (X, U): partials (6): ||Pi_C(BX+U) - U||^2, ||BX||^2,
 // ||U||^2, ||U - Pi_C(U)||^2, sum_l r_l ||(BX)_l||_q, 0.  Optionally writes
-// Pi_C(U) to Ufeas.
+// Pi_C(U) to Ufeas, and the first five terms per edge to rowstats (m x 5).
 constexpr int kEdgeKktNV = 6;
 int launch_edge_kkt(const DevGraph& g, int d, int qk, double gamma, const double* X,
-                    const double* U, double* Ufeas, double* partials, hipStream_t s);
+                    const double* U, double* Ufeas, double* partials, hipStream_t s,
+                    double* rowstats = nullptr);
 
 // ADMM edge step: Pi = Pi_C(sigma BX + L), Z <- BX + (L - Pi)/sigma,
 // L <- L + tau sigma (BX - Z), Q <- sigma Z - L, optional Uf <- Pi_C(L).
@@ -146,10 +147,11 @@ void launch_fused_flags(const DevGraph& g, int d, const double* X, double thr, i
 // also Dinv = 1 / (1 + sigma diag(B^T P B)) from the payload.  partials (4):
 // ||out||^2, 1/2 ||X - A||^2, <A, B^T Z>, ||B^T Z||^2.
 constexpr int kScatterNV = 4;
+// With rowstats (n x 4) the same four terms are also stored per vertex row.
 int launch_scatter(const DevGraph& g, int d, int qk, double cx, const double* X, double ca,
                    const double* A, double cz, const double* Z, double* out, bool diag,
                    Payload pl, double gamma, double sigma, double* Dinv, double* partials,
-                   hipStream_t s);
+                   hipStream_t s, double* rowstats = nullptr);
 
 // Newton matvec: out = c0 V + sigma sum_{l ~ i} P_l (v_i - v_other) with the
 // SSNAL payload (mode 0), P_l = I (mode 1, the ADMM matrix I + sigma B^T B),
@@ -211,6 +213,23 @@ void launch_lap_dinv(const DevGraph& g, int d, double c0, double sigma, double* 
 void launch_spread(const double* A, int64_t n, int d, double* work, double* out, hipStream_t s);
 int spread_work_size(int64_t n, int d);
 void launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
+// batched solves: copy union rows (and labels, offset to start at 0 per
+// instance) into per-instance output blocks: instance s owns rows
+// [vseg[s], vseg[s+1]); its gamma-t block starts at xoff[s] + t n_s d
+// (labels: loff[s] + t n_s)
+void launch_split(int64_t nU, int d, const double* X, const int* lab, const int64_t* vseg, int S,
+                  const int64_t* xoff, const int64_t* loff, int t, double* Xout, int* Lout,
+                  hipStream_t s);
+// out[i] = ||x_i||^2 for the n rows of X
+void launch_row_sqnorm(const double* X, int64_t n, int d, double* out, hipStream_t s);
+void launch_first_labels(const int* lab, const int64_t* vseg, int S, int* out, hipStream_t s);
+// so = src + voff, dso = dst + voff, wo = w; *bad |= 1 unless 0 <= src < dst < nloc
+void launch_offset_edges(int64_t m, const int* src, const int* dst, const double* w, int voff,
+                         int nloc, int* so, int* dso, double* wo, int* bad, hipStream_t s);
+// out[s * nv + c] = sum over rows r in [seg[s], seg[s + 1]) of rows[r * nv + c],
+// in row order (one block per segment)
+void launch_segsum(const double* rows, int nv, const int64_t* seg, int nseg, double* out,
+                   hipStream_t s);
 
 // ---- adjoint (adjoint.hip) ----------------------------------------------------
 // Per edge: delta = x_i - x_j; for an edge joining two clusters

@@ -6,6 +6,7 @@
 #include "solver.hpp"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -160,6 +161,12 @@ struct Solver::Impl {
     double last_bytes = 0;      // algorithmic bytes of one Newton matvec at the current state
     int64_t matvec_work = 0;    // matvec launches that did work (this gamma)
     double matvec_bytes_sum = 0;
+    // batched mode
+    const BatchSpec* batch = nullptr;
+    double floor_scale = 1.0;               // inner gradient floor relative to tol
+    std::vector<double> nA_inst;            // ||A|| per segment
+    std::vector<std::array<double, 7>> inst_res;
+    DevMem vrows, erows, vsum, esum;
 
     Impl(const DevGraph& graph, int d_, int qk_, const double* A_, hipStream_t s_,
          const ccm_options& opt, double tol_, std::string& e)
@@ -465,7 +472,7 @@ struct Solver::Impl {
                     numerical = true;
                     break;
                 }
-                if (ev.gn <= std::max(0.5 * tol, 0.2 * ev.rp)) break;
+                if (ev.gn <= std::max(0.5 * tol * floor_scale, 0.2 * ev.rp)) break;
                 if (out_of_time()) {
                     status = CCM_TIMEOUT;
                     return CCM_OK;
@@ -532,7 +539,17 @@ struct Solver::Impl {
                 numerical = true;
                 break;
             }
-            if (res[6] <= tol) {
+            double crit = res[6];
+            if (batch) {
+                CHK(batch_kkt(gamma));
+                crit = 0.0;
+                for (const auto& r : inst_res) crit = std::max(crit, r[6]);
+                if (!std::isfinite(crit)) {
+                    numerical = true;
+                    break;
+                }
+            }
+            if (crit <= tol) {
                 status = CCM_CONVERGED;
                 break;
             }
@@ -704,6 +721,52 @@ struct Solver::Impl {
         return CCM_OK;
     }
 
+    // per-segment KKT residuals of (X, U), each with the segment's own norms
+    ccm_status batch_kkt(double gamma) {
+        const BatchSpec& b = *batch;
+        const int S = b.S;
+        if (!vrows.p) {
+            HIPCHK(vrows.alloc(size_t(n) * kScatterNV * 8, s));
+            HIPCHK(erows.alloc(size_t(std::max<int64_t>(m, 1)) * 5 * 8, s));
+            HIPCHK(vsum.alloc(size_t(S) * kScatterNV * 8, s));
+            HIPCHK(esum.alloc(size_t(S) * 5 * 8, s));
+        }
+        {
+            Timed t(prof, CCM_K_SCATTER);
+            launch_scatter(g, d, qk, 1.0, X, -1.0, A, 1.0, U, bTmp.as<double>(), false, Payload{},
+                           gamma, sigma, nullptr, ps.as<double>(), s, vrows.as<double>());
+        }
+        {
+            Timed t(prof, CCM_K_EDGE);
+            if (m > 0)
+                launch_edge_kkt(g, d, qk, gamma, X, U, nullptr, pk.as<double>(), s,
+                                erows.as<double>());
+        }
+        launch_segsum(vrows.as<double>(), kScatterNV, b.vseg_dev, S, vsum.as<double>(), s);
+        std::vector<double> hv(size_t(S) * kScatterNV), he(size_t(S) * 5, 0.0);
+        if (m > 0) {
+            launch_segsum(erows.as<double>(), 5, b.eseg_dev, S, esum.as<double>(), s);
+            HIPCHK(hipMemcpyAsync(he.data(), esum.p, he.size() * 8, hipMemcpyDeviceToHost, s));
+        }
+        HIPCHK(hipMemcpyAsync(hv.data(), vsum.p, hv.size() * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        prof.harvest();
+        inst_res.assign(S, {0, 0, 0, 0, 0, 0, 0});
+        for (int i = 0; i < S; ++i) {
+            const double* v = &hv[size_t(i) * kScatterNV];
+            const double* e = &he[size_t(i) * 5];
+            const double RD = std::sqrt(v[0]) / (1.0 + nA_inst[i]);
+            const double nbx = std::sqrt(e[1]), nu = std::sqrt(e[2]);
+            const double RC = std::sqrt(e[0]) / (1.0 + nbx + nu);
+            const double RU = std::sqrt(e[3]) / (1.0 + nu);
+            const double fp = v[1] + e[4];
+            const double fd = v[2] - 0.5 * v[3];
+            const double eta = std::fabs(fp - fd) / (1.0 + std::fabs(fp) + std::fabs(fd));
+            inst_res[i] = {RD, RC, RU, eta, fp, fd, std::max(RD, std::max(RC, RU))};
+        }
+        return CCM_OK;
+    }
+
     ccm_status labels(int* lab_out, int* nclus_host) {
         Timed t(prof, CCM_K_OTHER);
         const double thr = 1e-5 * (1.0 + spread);
@@ -784,6 +847,77 @@ ccm_status Solver::run_path(const double* gammas, int T, const double* Xw, const
         I.matvec_work = 0;
         I.prof.take(st);
         if (stats) stats[t] = st;
+    }
+    HIPCHK(hipStreamSynchronize(I.s));
+    return CCM_OK;
+}
+
+ccm_status Solver::run_batched(const double* gammas, int T, const BatchSpec& b) {
+    Impl& I = *impl_;
+    std::string& err = I.err;
+    I.t_start = Clock::now();
+    I.batch = &b;
+    CHK(I.setup(nullptr, nullptr));
+    I.sigma = I.o.sigma0;
+    const int S = b.S;
+    // per-segment ||A||, and the inner gradient floor that makes the global
+    // test imply every segment's R_D test
+    {
+        DevMem rn, sums;
+        HIPCHK(rn.alloc(size_t(I.n) * 8, I.s));
+        HIPCHK(sums.alloc(size_t(S) * 8, I.s));
+        launch_row_sqnorm(I.A, I.n, I.d, rn.as<double>(), I.s);
+        launch_segsum(rn.as<double>(), 1, b.vseg_dev, S, sums.as<double>(), I.s);
+        std::vector<double> h(S);
+        HIPCHK(hipMemcpyAsync(h.data(), sums.p, size_t(S) * 8, hipMemcpyDeviceToHost, I.s));
+        HIPCHK(hipStreamSynchronize(I.s));
+        I.nA_inst.resize(S);
+        double mn = INFINITY;
+        for (int i = 0; i < S; ++i) {
+            I.nA_inst[i] = std::sqrt(h[i]);
+            mn = std::min(mn, I.nA_inst[i]);
+        }
+        I.floor_scale = (1.0 + mn) / (1.0 + I.nA);
+    }
+    DevMem lab, firsts;
+    HIPCHK(lab.alloc(size_t(I.n) * 4, I.s));
+    HIPCHK(firsts.alloc(size_t(S) * 4, I.s));
+    std::vector<int> hf(S);
+    for (int t = 0; t < T; ++t) {
+        const double gamma = gammas[t];
+        ccm_stats st;
+        std::memset(&st, 0, sizeof(st));
+        int stat = CCM_CONVERGED;
+        double res[7] = {0, 0, 0, 0, 0, 0, 0};
+        if (gamma == 0.0 || I.m == 0) {
+            HIPCHK(hipMemcpyAsync(I.X, I.A, size_t(I.N) * 8, hipMemcpyDeviceToDevice, I.s));
+            launch_fill(I.U, I.M, 0.0, I.s);
+            I.inst_res.assign(S, {0, 0, 0, 0, 0, 0, 0});
+        } else {
+            CHK(I.ssnal(gamma, stat, st, res));
+        }
+        int ncl = 0;
+        CHK(I.labels(lab.as<int>(), &ncl));
+        launch_split(I.n, I.d, I.X, lab.as<int>(), b.vseg_dev, S, b.xoff_dev, b.loff_dev, t,
+                     b.X_out_all, b.labels_all, I.s);
+        launch_first_labels(lab.as<int>(), b.vseg_dev, S, firsts.as<int>(), I.s);
+        HIPCHK(hipMemcpyAsync(hf.data(), firsts.p, size_t(S) * 4, hipMemcpyDeviceToHost, I.s));
+        HIPCHK(hipStreamSynchronize(I.s));
+        for (int i = 0; i < S; ++i) {
+            const int gi = b.inst[i];
+            const int next = (i + 1 < S) ? hf[i + 1] : ncl;
+            if (b.n_clusters_host) b.n_clusters_host[size_t(gi) * T + t] = next - hf[i];
+            const auto& r = I.inst_res[i];
+            if (b.kkt_host)
+                for (int c = 0; c < 4; ++c) b.kkt_host[(size_t(gi) * T + t) * 4 + c] = r[c];
+            if (b.status_host) {
+                int si = stat;
+                if (r[6] <= I.tol && stat != CCM_NUMERICAL) si = CCM_CONVERGED;
+                else if (stat == CCM_CONVERGED) si = CCM_MAX_ITER;
+                b.status_host[size_t(gi) * T + t] = si;
+            }
+        }
+        I.prof.take(st);
     }
     HIPCHK(hipStreamSynchronize(I.s));
     return CCM_OK;

@@ -260,6 +260,84 @@ __global__ void k_copy_bytes(const unsigned char* __restrict__ a, unsigned char*
         b[k] = a[k];
 }
 
+__global__ __launch_bounds__(kBlock) void k_segsum(const double* __restrict__ rows, int nv,
+                                                   const int64_t* __restrict__ seg,
+                                                   double* __restrict__ out) {
+    const int64_t a = seg[blockIdx.x], b = seg[blockIdx.x + 1];
+    for (int c = 0; c < nv; ++c) {
+        __shared__ double red[kBlock];
+        double t = 0.0;
+        for (int64_t r = a + threadIdx.x; r < b; r += kBlock) t += rows[r * nv + c];
+        red[threadIdx.x] = t;
+        __syncthreads();
+        for (int off = kBlock / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[int64_t(blockIdx.x) * nv + c] = red[0];
+        __syncthreads();
+    }
+}
+
+// scatter union rows back to per-instance output blocks (batched solves)
+__global__ __launch_bounds__(kBlock) void k_split(int64_t nU, int d, const double* __restrict__ X,
+                                                  const int* __restrict__ lab,
+                                                  const int64_t* __restrict__ vseg, int S,
+                                                  const int64_t* __restrict__ xoff,
+                                                  const int64_t* __restrict__ loff, int t,
+                                                  double* __restrict__ Xout,
+                                                  int* __restrict__ Lout) {
+    const int64_t N = nU * d;
+    for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < N;
+         e += int64_t(gridDim.x) * kBlock) {
+        const int64_t i = e / d, k = e % d;
+        int lo = 0, hi = S;  // last segment with vseg[s] <= i
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (vseg[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        const int64_t v0 = vseg[lo], ns = vseg[lo + 1] - v0, li = i - v0;
+        Xout[xoff[lo] + int64_t(t) * ns * d + li * d + k] = X[e];
+        if (Lout && k == 0) Lout[loff[lo] + int64_t(t) * ns + li] = lab[i] - lab[v0];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_sqnorm(const double* __restrict__ X, int64_t n,
+                                                       int d, double* __restrict__ out) {
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * kBlock) {
+        double t = 0.0;
+        for (int k = 0; k < d; ++k) t += X[i * d + k] * X[i * d + k];
+        out[i] = t;
+    }
+}
+
+__global__ void k_first_labels(const int* __restrict__ lab, const int64_t* __restrict__ vseg,
+                               int S, int* __restrict__ out) {
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x)
+        out[s] = lab[vseg[s]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_offset_edges(int64_t m, const int* __restrict__ src,
+                                                         const int* __restrict__ dst,
+                                                         const double* __restrict__ w,
+                                                         int voff, int nloc,
+                                                         int* __restrict__ so,
+                                                         int* __restrict__ dso,
+                                                         double* __restrict__ wo, int* bad) {
+    int b = 0;
+    for (int64_t l = int64_t(blockIdx.x) * kBlock + threadIdx.x; l < m;
+         l += int64_t(gridDim.x) * kBlock) {
+        const int a = src[l], c = dst[l];
+        if (a < 0 || c >= nloc || a >= c) b = 1;
+        so[l] = a + voff;
+        dso[l] = c + voff;
+        wo[l] = w[l];
+    }
+    if (b) atomicOr(bad, 1);
+}
+
 constexpr int kSpreadBlocks = 128;
 
 }  // namespace
@@ -341,6 +419,34 @@ void launch_spread(const double* A, int64_t n, int d, double* work, double* out,
                        kSpreadBlocks, n, d, mean);
     hipLaunchKernelGGL(k_rowdev_max, dim3(kSpreadBlocks), dim3(kBlock), 0, s, A, n, d, mean, bmax);
     hipLaunchKernelGGL(k_max_sqrt, dim3(1), dim3(kBlock), 0, s, bmax, kSpreadBlocks, out);
+}
+
+void launch_segsum(const double* rows, int nv, const int64_t* seg, int nseg, double* out,
+                   hipStream_t s) {
+    if (nseg <= 0) return;
+    hipLaunchKernelGGL(k_segsum, dim3(nseg), dim3(kBlock), 0, s, rows, nv, seg, out);
+}
+
+void launch_split(int64_t nU, int d, const double* X, const int* lab, const int64_t* vseg, int S,
+                  const int64_t* xoff, const int64_t* loff, int t, double* Xout, int* Lout,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_split, dim3(flat_grid(nU * d)), dim3(kBlock), 0, s, nU, d, X, lab, vseg,
+                       S, xoff, loff, t, Xout, Lout);
+}
+
+void launch_row_sqnorm(const double* X, int64_t n, int d, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_row_sqnorm, dim3(flat_grid(n)), dim3(kBlock), 0, s, X, n, d, out);
+}
+
+void launch_first_labels(const int* lab, const int64_t* vseg, int S, int* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_first_labels, dim3((S + 255) / 256), dim3(256), 0, s, lab, vseg, S, out);
+}
+
+void launch_offset_edges(int64_t m, const int* src, const int* dst, const double* w, int voff,
+                         int nloc, int* so, int* dso, double* wo, int* bad, hipStream_t s) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_offset_edges, dim3(flat_grid(m)), dim3(kBlock), 0, s, m, src, dst, w, voff,
+                       nloc, so, dso, wo, bad);
 }
 
 void launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s) {

@@ -132,12 +132,14 @@ struct ScatterOut {
     const double* A;
     double* out;
     double* Dinv;
+    double* rowstats;  // optional n x 4: the four partial-sum terms of each vertex row
 };
 
 template <int LPR, int NPER, bool DIAG>
 __device__ __forceinline__ void scatter_finish(int64_t v, int d, int gl, const ScatterOut& so,
                                                const double (&acc)[NPER], const double (&dg)[NPER],
                                                double (&acc4)[kScatterNV]) {
+    double r4[kScatterNV] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int t = 0; t < NPER; ++t) {
         const int k = gl + LPR * t;
@@ -147,11 +149,20 @@ __device__ __forceinline__ void scatter_finish(int64_t v, int d, int gl, const S
             const double o = so.cx * xv + so.ca * av + so.cz * acc[t];
             so.out[v * d + k] = o;
             const double dx = xv - av;
-            acc4[0] += o * o;
-            acc4[1] += 0.5 * dx * dx;
-            acc4[2] += av * acc[t];
-            acc4[3] += acc[t] * acc[t];
+            r4[0] += o * o;
+            r4[1] += 0.5 * dx * dx;
+            r4[2] += av * acc[t];
+            r4[3] += acc[t] * acc[t];
             if constexpr (DIAG) so.Dinv[v * d + k] = 1.0 / (1.0 + so.sigma * dg[t]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kScatterNV; ++c) acc4[c] += r4[c];
+    if (so.rowstats) {
+#pragma unroll
+        for (int c = 0; c < kScatterNV; ++c) {
+            const double tot = group_sum<LPR>(r4[c]);
+            if (gl == 0) so.rowstats[v * kScatterNV + c] = tot;
         }
     }
 }
@@ -463,9 +474,10 @@ __global__ __launch_bounds__(kBlock) void k_matvec_fix(DevGraph g, int d,
 
 int launch_scatter(const DevGraph& g, int d, int qk, double cx, const double* X, double ca,
                    const double* A, double cz, const double* Z, double* out, bool diag, Payload pl,
-                   double gamma, double sigma, double* Dinv, double* partials, hipStream_t s) {
+                   double gamma, double sigma, double* Dinv, double* partials, hipStream_t s,
+                   double* rowstats) {
     int total = 0;
-    ScatterOut so{cx, ca, cz, sigma, X, A, out, Dinv};
+    ScatterOut so{cx, ca, cz, sigma, X, A, out, Dinv, rowstats};
     dispatch_row(d, [&](auto L, auto N) {
         constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
         const int g1 = g.nchunks > 0 ? row_grid(g.nchunks, lpr) : 0;

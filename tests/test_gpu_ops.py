@@ -164,3 +164,20 @@ def test_stream_copy():
     b = torch.empty_like(a)
     ms = ccm.ccm_stream_copy(a, b, a.numel() * 8, repeats=3)
     assert torch.equal(a, b) and ms > 0
+
+
+@pytest.mark.parametrize("d", [2, 5, 64])
+def test_l1_ball_projection_tiny_radius(d):
+    # radii below the rounding resolution of max |y_k|: the projection is 0
+    # (regression: support pruning must not cycle to an infeasible point)
+    torch, ccm = need_gpu()
+    rng = np.random.default_rng(700 + d)
+    m = 300
+    Y = rng.normal(size=(m, d)) * 3.0
+    w = 10.0 ** rng.uniform(-24, -12, size=m)
+    w[::7] = rng.uniform(0.1, 1.0, size=w[::7].shape)  # and some ordinary radii
+    g = 1e-3
+    P = host(ccm.ccm_op_project(dev(Y), dev(w), g, np.inf))
+    Pr = ops.project(Y, g * w, np.inf)
+    assert np.allclose(P, Pr, rtol=1e-12, atol=1e-14)
+    assert np.all(np.abs(P).sum(1) <= g * w * (1 + 1e-12) + 1e-300)

@@ -241,3 +241,63 @@ def test_ccmsolve_autograd():
     assert torch.allclose(At.grad, dA, rtol=1e-8, atol=1e-10)
     assert torch.allclose(lw.grad, dlw, rtol=1e-8, atol=1e-10)
     assert abs(float(gam.grad) - dg) <= 1e-8 * (1 + abs(dg))
+
+
+def _instances(count, seed, n_lo=30, n_hi=90, dims=(2, 3, 8), qs=(1.0, 2.0, np.inf)):
+    insts = synthdata.instances(seed=seed, count=count, n_lo=n_lo, n_hi=n_hi, dims=dims,
+                                blobs_lo=2, blobs_hi=4, qs=qs)
+    out = []
+    for it in insts:
+        A = it["A"]
+        src, dst, w, *_ = oracle.knn_graph(A, 5, None)
+        out.append(dict(A=A, src=src, dst=dst, w=w, q=it["q"]))
+    return out
+
+
+def test_batched_matches_single_instance_solves():
+    torch, ccm = need_gpu()
+    insts = _instances(9, seed=21)
+    gammas = synthdata.gamma_grid(-2, 0.5, 4)
+    dev_insts = [dict(A=dev(i["A"]), src=dev(i["src"].astype(np.int32)),
+                      dst=dev(i["dst"].astype(np.int32)), w=dev(i["w"]), q=i["q"]) for i in insts]
+    res = ccm.ccm_solve_path_batched(dev_insts, gammas, 1e-8)
+    for k, inst in enumerate(insts):
+        ref = oracle.solve_path(inst["A"], inst["src"], inst["dst"], inst["w"], gammas,
+                                inst["q"], 1e-10)
+        B = oracle.incidence(inst["src"], inst["dst"], inst["A"].shape[0])
+        S = oracle.fusion_scale(inst["A"])
+        for t, g in enumerate(gammas):
+            X = host(res[k]["X"][t])
+            assert res[k]["status"][t] == 0, (k, t, res[k]["kkt"][t])
+            assert res[k]["kkt"][t][:3].max() <= 1e-8
+            assert rel(X, ref["X"][t]) <= 1e-6, (k, t)
+            mg = oracle.fusion_margins(ref["X"][t], ref["U"][t], inst["src"], inst["dst"],
+                                       inst["w"], g, inst["q"], S)
+            if mg.min() > 1e-4:
+                assert np.array_equal(host(res[k]["labels"][t]), ref["labels"][t])
+                assert res[k]["n_clusters"][t] == ref["n_clusters"][t]
+
+
+def test_batched_rejects_bad_descriptor():
+    torch, ccm = need_gpu()
+    insts = _instances(2, seed=22)
+    d_insts = [dict(A=dev(i["A"]), src=dev(i["src"].astype(np.int32)),
+                    dst=dev(i["dst"].astype(np.int32)), w=dev(i["w"]), q=i["q"]) for i in insts]
+    bad = dict(d_insts[1])
+    bad["dst"] = bad["dst"].clone()
+    bad["dst"][0] = insts[1]["A"].shape[0] + 3  # outside the instance
+    with pytest.raises(ccm.CcmError) as e:
+        ccm.ccm_solve_path_batched([d_insts[0], bad], [0.1], 1e-6)
+    assert e.value.status == 1
+
+
+def test_qinf_tiny_weights_path():
+    # k-NN Gaussian weights span many decades; q = inf radii reach 1e-22
+    torch, ccm = need_gpu()
+    insts = synthdata.instances(count=40)
+    it = [i for i in insts if i["q"] == np.inf and i["d"] == 2][0]
+    A = it["A"]  # n = 3156, weights down to 2e-35
+    src, dst, w, *_ = oracle.knn_graph(A, 10, None)
+    assert w.min() < 1e-30
+    gammas = [1e-3, 1e-2]
+    _compare_path(A, src, dst, w, gammas, np.inf, "ssnal", 1e-7, x_tol=1e-5)
