@@ -18,6 +18,10 @@ by their summed HIP-event durations (recorded by the library on its launch
 stream).  The cpu_baseline object times the oracle (CPU, FP64) on a bounded
 sample of the same workload and scales it to one path.
 
+The same JSON line also reports the growth forms beside the plain path:
+"adjoint" (n = 20000, d = 32: tight forward solve + VJP) and "batched" (512
+instances of uneven n, d and q, 10 gammas each, one batched call).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 from __future__ import annotations
@@ -131,6 +135,62 @@ def cpu_baseline(A_np, wl, budget_s=20.0):
                 measured_s=round(t_knn * len(rows) / n + t_solve, 3))
 
 
+def batched_leg(ccm, torch, count, budget_s):
+    """512 independent instances (uneven n, d, q), 10 gammas each, one call."""
+    import synthdata
+    insts = synthdata.instances(count=count)
+    dev = []
+    for it in insts:
+        A = torch.from_numpy(it["A"]).cuda()
+        src, dst, w, _ = ccm.ccm_build_knn_graph(A, 10, 0.0)
+        dev.append(dict(A=A, src=src, dst=dst, w=w, q=it["q"]))
+    torch.cuda.synchronize()
+    g = np.logspace(-3, 1, 10)
+    o = ccm.ccm_default_options(time_budget_s=budget_s)
+    t0 = time.perf_counter()
+    res = ccm.ccm_solve_path_batched(dev, g, 1e-6, opts=o)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = np.array([r["status"] for r in res])              # [instances, gammas]
+    kk = np.array([r["kkt"][:, :3].max(axis=1) for r in res])  # per (instance, gamma)
+    conv = int((st == 0).sum())
+    return {"workload": f"instances{count}: n~U[100,5000], d in {{2,8,32,128}}, q in {{1,2,inf}}, "
+                        "k=10, 10 gammas [1e-3,1e1], SSNAL to per-instance KKT 1e-6",
+            "instances": count, "sum_n": int(sum(i["n"] for i in insts)),
+            "sum_m": int(sum(int(x["src"].numel()) for x in dev)),
+            "seconds": round(el, 3), "instance_paths_per_s": round(count / el, 2),
+            "converged_pairs": conv, "total_pairs": int(st.size),
+            "max_kkt_converged": float(kk[st == 0].max()) if conv else None,
+            "status_counts": [int(c) for c in np.bincount(st.ravel(), minlength=4)],
+            "time_budget_s": budget_s}
+
+
+def adjoint_leg(ccm, torch):
+    """n = 20000, d = 32, 8 blobs, q = 2, gamma = 0.5: tight forward solve +
+    VJP of L = sum ||x_i - t_i||^2 with respect to A, log w and gamma."""
+    import synthdata
+    A_np, _, T_np = synthdata.mixture32()
+    A = torch.from_numpy(A_np).cuda()
+    T = torch.from_numpy(T_np).cuda()
+    src, dst, w, _ = ccm.ccm_build_knn_graph(A, 10, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = ccm.ccm_solve_path(A, src, dst, w, [0.5], 2.0, 1e-10)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    X = out["X"][0]
+    dA, dlw, dg, it = ccm.ccm_path_vjp(A, src, dst, w, 0.5, X, out["labels"][0], 2 * (X - T),
+                                       tol=1e-12)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"workload": "mixture32_n20000: n=20000 d=32 8 Gaussians, k=10, q=2, gamma=0.5, "
+                        "L=sum||x_i-t_i||^2",
+            "m": int(src.numel()), "forward_seconds": round(t1 - t0, 3),
+            "forward_kkt": float(out["kkt"][0][:3].max()), "clusters": int(out["n_clusters"][0]),
+            "vjp_seconds": round(t2 - t1, 3), "vjp_cg_iterations": int(it),
+            "dL_dgamma": dg}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +198,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mixture64_n10000", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--batched-count", type=int, default=512)
+    ap.add_argument("--batched-budget", type=float, default=90.0,
+                    help="wall-clock budget (s) of each (q, d) group of the batched leg")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-kernel HIP events (roofline then omitted)")
     args = ap.parse_args()
@@ -251,6 +316,12 @@ def main():
         "copy_kernel_gbs": round(copy_gbs, 1),
         "cpu_baseline": None,
     }
+    if not args.no_adjoint:
+        log("adjoint leg ...")
+        rec["adjoint"] = adjoint_leg(ccm, torch)
+    if not args.no_batched:
+        log("batched leg ...")
+        rec["batched"] = batched_leg(ccm, torch, args.batched_count, args.batched_budget)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
         rec["cpu_baseline"] = cpu_baseline(A_np, wl)

@@ -80,23 +80,40 @@ struct Prof {
         used += 2;
         open_cls = -1;
     }
-    // index of the most recent recorded pair (for reclassification)
-    int last_pair() const { return on && used >= 2 ? int(used / 2) - 1 : -1; }
-    void reclass(int pair, int c) {
-        if (on && pair >= 0 && size_t(pair) < used / 2) cls[pair] = c;
+    // Pairs carry ids base + local index, so they can be reclassified or
+    // harvested while later pairs are still in flight.
+    size_t base = 0;
+    int64_t last_pair() const { return on && used >= 2 ? int64_t(base + used / 2) - 1 : -1; }
+    int64_t next_pair() const { return int64_t(base + used / 2); }
+    void reclass(int64_t id, int c) {
+        if (!on || id < int64_t(base)) return;
+        const size_t loc = size_t(id) - base;
+        if (loc < used / 2) cls[loc] = c;
     }
-    // after a stream synchronisation: accumulate every recorded pair
-    void harvest() {
+    // accumulate the pairs with id < id_end (their events have completed)
+    void harvest_until(int64_t id_end) {
         if (!on) return;
-        for (size_t k = 0; k + 1 < used; k += 2) {
+        const size_t have = used / 2;
+        const size_t np =
+            std::min(have, size_t(std::max<int64_t>(0, id_end - int64_t(base))));
+        for (size_t k = 0; k < np; ++k) {
             float t = 0.f;
-            if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) == hipSuccess) {
-                ms[cls[k / 2]] += t;
-                calls[cls[k / 2]] += 1;
+            if (hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]) == hipSuccess) {
+                ms[cls[k]] += t;
+                calls[cls[k]] += 1;
             }
         }
-        used = 0;
+        const size_t rem = have - np;
+        for (size_t r = 0; r < rem; ++r) {
+            std::swap(ev[2 * r], ev[2 * (np + r)]);
+            std::swap(ev[2 * r + 1], ev[2 * (np + r) + 1]);
+            cls[r] = cls[np + r];
+        }
+        used = rem * 2;
+        base += np;
     }
+    // after a stream synchronisation: accumulate every recorded pair
+    void harvest() { harvest_until(next_pair()); }
     void take(ccm_stats& st) {
         for (int c = 0; c < CCM_NK; ++c) {
             st.kern_ms[c] = ms[c];
@@ -147,7 +164,8 @@ struct Solver::Impl {
     DevMem pe, pet, ps, pst, pt, pk, pm, pm2, pupd0, pupd1, pwu0, pwu1, dsc, cgstate, cgflag,
         spread_work;
     double* hs = nullptr;
-    int* hflag = nullptr;
+    int* hflag = nullptr;          // [0..1] status, [4..5] second pending chunk
+    hipEvent_t cg_ev[2] = {nullptr, nullptr};
     CgBufs cg{};
 
     double *X = nullptr, *Xt = nullptr, *G = nullptr, *Gt = nullptr, *Dinv = nullptr,
@@ -178,6 +196,8 @@ struct Solver::Impl {
     ~Impl() {
         if (hs) (void)hipHostFree(hs);
         if (hflag) (void)hipHostFree(hflag);
+        for (auto e : cg_ev)
+            if (e) (void)hipEventDestroy(e);
     }
 
     ccm_status alloc() {
@@ -223,7 +243,8 @@ struct Solver::Impl {
         HIPCHK(cgflag.alloc(4 * 4, s));
         HIPCHK(spread_work.alloc(size_t(spread_work_size(n, d)) * 8, s));
         HIPCHK(hipHostMalloc((void**)&hs, kNS * 8, hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void**)&hflag, 4 * 4, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&hflag, 8 * 4, hipHostMallocDefault));
+        for (auto& e : cg_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         std::memset(hs, 0, kNS * 8);
         X = bX.as<double>();
         Xt = bXt.as<double>();
@@ -352,19 +373,33 @@ struct Solver::Impl {
             cg.nparts_mv = launch_matvec(g, d, qk, mode, cg.u, Pic, p, gamma, sigma, 1.0, nullptr,
                                          cg.w, cg.wu[0], CgSkip{}, s);
         }
+        // Chunks of CG iterations are issued one ahead: chunk k + 1 is
+        // enqueued before the host waits for chunk k's status, so the host's
+        // decision overlaps device work.  Launches issued after convergence
+        // return at once (device-side flag) and are timed as "other".
         const int chunk = std::max(1, o.cg_chunk);
         int j = 0;
-        hflag[0] = 0;
-        hflag[1] = 0;
-        std::vector<int> mv_pair(chunk, -1), upd_pair(chunk, -1);
-        while (j < o.cg_max_iter) {
-            const int j0 = j;
+        struct Pending {
+            int j0 = 0, j1 = 0;
+            int64_t pid_end = 0;
+            std::vector<int64_t> upd, mv;
+            int* hf = nullptr;
+            hipEvent_t e = nullptr;
+        } P[2];
+        P[0].hf = hflag;
+        P[1].hf = hflag + 4;
+        P[0].e = cg_ev[0];
+        P[1].e = cg_ev[1];
+        auto issue = [&](Pending& q) -> ccm_status {
+            q.j0 = j;
+            q.upd.clear();
+            q.mv.clear();
             for (int c = 0; c < chunk && j < o.cg_max_iter; ++c, ++j) {
                 {
                     Timed t(prof, CCM_K_CGUPDATE);
                     launch_cg_update(N, j, Dv, cg, thr, s);
                 }
-                upd_pair[c] = prof.last_pair();
+                q.upd.push_back(prof.last_pair());
                 {
                     Timed t(prof, CCM_K_MATVEC);
                     CgSkip sk;
@@ -375,23 +410,45 @@ struct Solver::Impl {
                     launch_matvec(g, d, qk, mode, cg.u, Pic, p, gamma, sigma, 1.0, nullptr, cg.w,
                                   cg.wu[(j + 1) & 1], sk, s);
                 }
-                mv_pair[c] = prof.last_pair();
+                q.mv.push_back(prof.last_pair());
             }
-            HIPCHK(hipMemcpyAsync(hflag, cg.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            // launches issued after convergence return at once: time them as
-            // "other" so the matvec class holds only matvecs that did work
-            if (hflag[0]) {
-                const int done_at = hflag[1];
-                for (int c = 0; c < j - j0; ++c) {
-                    const int jj = j0 + c;
-                    if (jj >= done_at) prof.reclass(upd_pair[c], CCM_K_OTHER);
-                    if (jj + 1 >= done_at) prof.reclass(mv_pair[c], CCM_K_OTHER);
+            q.j1 = j;
+            HIPCHK(hipMemcpyAsync(q.hf, cg.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipEventRecord(q.e, s));
+            q.pid_end = prof.next_pair();
+            return CCM_OK;
+        };
+        int cur = 0;
+        bool done = false;
+        int done_at = 0;
+        CHK(issue(P[0]));
+        while (true) {
+            const bool more = j < o.cg_max_iter;
+            if (more) CHK(issue(P[cur ^ 1]));
+            HIPCHK(hipEventSynchronize(P[cur].e));
+            const Pending& q = P[cur];
+            if (q.hf[0]) {
+                done = true;
+                done_at = q.hf[1];
+                for (size_t c = 0; c < q.upd.size(); ++c) {
+                    const int jj = q.j0 + int(c);
+                    if (jj >= done_at) prof.reclass(q.upd[c], CCM_K_OTHER);
+                    if (jj + 1 >= done_at) prof.reclass(q.mv[c], CCM_K_OTHER);
+                }
+                if (more) {
+                    const Pending& nx = P[cur ^ 1];
+                    for (size_t c = 0; c < nx.upd.size(); ++c) {
+                        prof.reclass(nx.upd[c], CCM_K_OTHER);
+                        prof.reclass(nx.mv[c], CCM_K_OTHER);
+                    }
                 }
             }
-            prof.harvest();
-            if (hflag[0]) break;
+            prof.harvest_until(q.pid_end);
+            if (done || !more) break;
+            cur ^= 1;
         }
+        hflag[0] = done ? 1 : 0;
+        hflag[1] = done ? done_at : j;
         iters = hflag[0] ? hflag[1] : j;
         // matvec launches that did work: the initial one plus one per
         // iteration whose residual was still above the threshold
