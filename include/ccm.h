@@ -134,6 +134,18 @@ ccm_status ccm_build_knn_graph(const double* A, int64_t n, int64_t d, int32_t k,
                                int32_t* src, int32_t* dst, double* w, int64_t m_cap,
                                int64_t* m_out_host, double* phi_out_host, hipStream_t stream);
 
+/* The same graph for quantised data given as integer codes: the points are
+ * a_i = scale * K_i with K an n x d uint8 array (device), and
+ * d^2(i, j) = (double)D_ij * scale * scale with D_ij = sum_k (K_ik - K_jk)^2
+ * computed exactly in integer arithmetic (int8 matrix cores with int32
+ * accumulation); ties broken by the smaller j.  1 <= d <= 8192.  Other
+ * arguments, outputs and errors as for ccm_build_knn_graph.
+ */
+ccm_status ccm_build_knn_graph_u8(const uint8_t* K, int64_t n, int64_t d, double scale, int32_t k,
+                                  double phi, int32_t* src, int32_t* dst, double* w,
+                                  int64_t m_cap, int64_t* m_out_host, double* phi_out_host,
+                                  hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Clustering path (Section 1: solve (CCM) for gamma_1 < ... < gamma_T; the
  * solutions are continuous in gamma, so each gamma is warm-started from the

@@ -102,3 +102,47 @@ def knn_graph(A, k, phi=None):
     w = np.exp(-phi * dist)
     keep = w > 0
     return src[keep], dst[keep], w[keep], phi, idx, d2
+
+
+def knn_brute_u8(K, k, rows=None, block=64):
+    """Exact integer k-NN of integer codes K (squared distances summed in
+    int64, no rounding), self excluded, order (D, index).
+    Returns (idx int32 [r, k], D int64 [r, k])."""
+    K = np.asarray(K).astype(np.int64)
+    n = K.shape[0]
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    kk = min(k, n - 1)
+    idx = np.empty((rows.shape[0], kk), dtype=np.int32)
+    D = np.empty((rows.shape[0], kk), dtype=np.int64)
+    for s in range(0, rows.shape[0], block):
+        rr = rows[s:s + block]
+        diff = K[rr][:, None, :] - K[None, :, :]
+        Db = (diff * diff).sum(axis=2)
+        Db[np.arange(rr.shape[0]), rr] = np.iinfo(np.int64).max
+        order = np.argsort(Db, axis=1, kind="stable")[:, :kk]
+        idx[s:s + block] = order
+        D[s:s + block] = np.take_along_axis(Db, order, axis=1)
+    return idx, D
+
+
+def knn_graph_u8(K, scale, k, phi=None):
+    """Graph of the points scale * K from exact integer distances:
+    d^2 = float(D) * scale * scale, otherwise as knn_graph."""
+    K = np.asarray(K)
+    n = K.shape[0]
+    idx, D = knn_brute_u8(K, k)
+    d2 = D.astype(np.float64) * scale * scale
+    if phi is None or phi <= 0:
+        med = float(np.median(d2)) if d2.size else 0.0
+        phi = 1.0 / med if med > 0 else 1.0
+    ii = np.repeat(np.arange(n), idx.shape[1])
+    jj = idx.reshape(-1).astype(np.int64)
+    a = np.minimum(ii, jj)
+    b = np.maximum(ii, jj)
+    key = a * n + b
+    key_u, first = np.unique(key, return_index=True)
+    src = (key_u // n).astype(np.int32)
+    dst = (key_u % n).astype(np.int32)
+    w = np.exp(-phi * d2.reshape(-1)[first])
+    keep = w > 0
+    return src[keep], dst[keep], w[keep], phi, idx, d2

@@ -36,7 +36,7 @@ EXPORTED_SYMBOLS = [
     "ccm_build_knn_graph", "ccm_solve_path", "ccm_canonical_edge_count",
     "ccm_op_gather", "ccm_op_project", "ccm_op_prox", "ccm_op_scatter",
     "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy", "ccm_path_vjp",
-    "ccm_solve_path_batched",
+    "ccm_solve_path_batched", "ccm_build_knn_graph_u8",
 ]
 
 
@@ -119,6 +119,7 @@ def lib():
         "ccm_stream_copy": [P, P, I64, I32, P, P],
         "ccm_path_vjp": [P, I64, I64, P, P, P, I64, F64, F64, P, P, P, P, P, P, F64, I32, P, P],
         "ccm_solve_path_batched": [P, I32, P, P, P, P, P, I32, F64, P, P, P, P, P, P, P],
+        "ccm_build_knn_graph_u8": [P, I64, I64, F64, I32, F64, P, P, P, I64, P, P, P],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -199,6 +200,27 @@ def ccm_build_knn_graph(A, k, phi=0.0, m_cap=None, stream=None):
     _check(lib().ccm_build_knn_graph(_ptr(A), n, d, int(k), float(phi), _ptr(src), _ptr(dst),
                                      _ptr(w), m_cap, ctypes.byref(m_out), ctypes.byref(phi_out),
                                      _stream(stream)))
+    m = m_out.value
+    return src[:m], dst[:m], w[:m], phi_out.value
+
+
+def ccm_build_knn_graph_u8(K, scale, k, phi=0.0, m_cap=None, stream=None):
+    """k-NN Gaussian weight graph of quantised points scale * K (K: device
+    uint8 [n, d]) with exact integer distances.  Returns (src, dst, w, phi)."""
+    torch = _torch()
+    if K.dtype != torch.uint8:
+        raise ValueError("uint8 tensor expected")
+    n, d = K.shape
+    m_cap = int(m_cap if m_cap is not None else n * k)
+    src = torch.empty(max(m_cap, 1), dtype=torch.int32, device=K.device)
+    dst = torch.empty_like(src)
+    w = torch.empty(max(m_cap, 1), dtype=torch.float64, device=K.device)
+    m_out = ctypes.c_int64(0)
+    phi_out = ctypes.c_double(0.0)
+    _check(lib().ccm_build_knn_graph_u8(_ptr(K), n, d, float(scale), int(k), float(phi),
+                                        _ptr(src), _ptr(dst), _ptr(w), m_cap,
+                                        ctypes.byref(m_out), ctypes.byref(phi_out),
+                                        _stream(stream)))
     m = m_out.value
     return src[:m], dst[:m], w[:m], phi_out.value
 

@@ -136,6 +136,30 @@ ccm_status ccm_build_knn_graph(const double* A, int64_t n, int64_t d, int32_t k,
     return CCM_OK;
 }
 
+ccm_status ccm_build_knn_graph_u8(const uint8_t* K, int64_t n, int64_t d, double scale, int32_t k,
+                                  double phi, int32_t* src, int32_t* dst, double* w,
+                                  int64_t m_cap, int64_t* m_out_host, double* phi_out_host,
+                                  hipStream_t stream) {
+    g_err.clear();
+    if (!K || !src || !dst || !w || !m_out_host) return fail(CCM_E_INVALID, "null argument");
+    if (n < 2) return fail(CCM_E_INVALID, "n must be >= 2");
+    if (d < 1 || d > 8192) return fail(CCM_E_INVALID, "need 1 <= d <= 8192");
+    if (n > (int64_t(1) << 30)) return fail(CCM_E_INVALID, "too large");
+    if (k < 1 || k > 32 || k > n - 1) return fail(CCM_E_INVALID, "need 1 <= k <= min(n - 1, 32)");
+    if (!(scale > 0) || !std::isfinite(scale)) return fail(CCM_E_INVALID, "scale must be > 0");
+    if (m_cap < 0) return fail(CCM_E_INVALID, "m_cap < 0");
+    if (std::isnan(phi) || std::isinf(phi)) return fail(CCM_E_INVALID, "phi must be finite");
+    std::string err;
+    int64_t mo = 0;
+    double po = 0;
+    ccm_status st = knn_graph_u8(K, n, int(d), scale, k, phi, src, dst, w, m_cap, mo, po, stream,
+                                 err);
+    *m_out_host = mo;
+    if (st != CCM_OK) return fail(st, err);
+    if (phi_out_host) *phi_out_host = po;
+    return CCM_OK;
+}
+
 ccm_status ccm_canonical_edge_count(const int32_t* src, const int32_t* dst, const double* w,
                                     int64_t m, int64_t n, int64_t* m_canon_host,
                                     hipStream_t stream) {

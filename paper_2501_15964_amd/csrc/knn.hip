@@ -195,6 +195,144 @@ __global__ void k_median(const double* __restrict__ sorted, int64_t cnt, double*
     }
 }
 
+// ---- quantised data: exact integer distances on int8 MFMA ------------------
+//
+// Codes K in [0, 255] are centred to K - 128 in int8 and padded to a
+// multiple of 64 features; then d2(i, j) = |a_i|^2 + |a_j|^2 - 2 a_i.a_j is
+// exact in int32 (|a_i . a_j| <= 784 * 128^2 < 2^31 for d <= 1024 ... and in
+// general d * 128^2 < 2^31).  A block owns 64 query rows (16 per wave);
+// candidate tiles of 64 rows are staged in LDS; each wave accumulates four
+// 16 x 16 tiles with v_mfma_i32_16x16x64_i8 (16 int8 per lane per operand;
+// A and B place the same k values in the same lane slots, so the dot
+// product does not depend on the hardware's k numbering).  The 64 x 64
+// distance tile goes through LDS to a top-KP scan by 4 threads per row.
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int kUQ = 64;   // query rows per block
+constexpr int kUC = 64;   // candidate rows per tile
+
+__global__ __launch_bounds__(kBlock) void k_u8_prep(const unsigned char* __restrict__ K, int64_t n,
+                                                    int d, int dp,
+                                                    signed char* __restrict__ Kc,
+                                                    int* __restrict__ nrm) {
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * kBlock) {
+        int s = 0;
+        for (int k = 0; k < dp; ++k) {
+            const int v = k < d ? int(K[i * d + k]) - 128 : 0;
+            Kc[i * dp + k] = static_cast<signed char>(v);
+            s += v * v;
+        }
+        nrm[i] = s;
+    }
+}
+
+template <int KP>
+__device__ __forceinline__ void knn_insert_i(int (&bd)[KP], int (&bi)[KP], int dv, int j) {
+    if (!(dv < bd[KP - 1] || (dv == bd[KP - 1] && j < bi[KP - 1]))) return;
+    bool placed = false;
+#pragma unroll
+    for (int p = KP - 1; p >= 1; --p) {
+        if (!placed) {
+            if (dv < bd[p - 1] || (dv == bd[p - 1] && j < bi[p - 1])) {
+                bd[p] = bd[p - 1];
+                bi[p] = bi[p - 1];
+            } else {
+                bd[p] = dv;
+                bi[p] = j;
+                placed = true;
+            }
+        }
+    }
+    if (!placed) {
+        bd[0] = dv;
+        bi[0] = j;
+    }
+}
+
+template <int KP>
+__global__ __launch_bounds__(kBlock) void k_knn_u8(const signed char* __restrict__ Kc,
+                                                   const int* __restrict__ nrm, int64_t n, int dp,
+                                                   int64_t cols_per_split, double* __restrict__ pd,
+                                                   int* __restrict__ pi) {
+    extern __shared__ unsigned char smem[];
+    signed char* Bs = reinterpret_cast<signed char*>(smem);         // kUC x dp
+    int* Ds = reinterpret_cast<int*>(smem + size_t(kUC) * dp);      // kUQ x kUC
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int64_t q0 = int64_t(blockIdx.x) * kUQ;
+    const int64_t c_begin = int64_t(blockIdx.y) * cols_per_split;
+    int64_t c_end = c_begin + cols_per_split;
+    if (c_end > n) c_end = n;
+    // scan role: row tid / 4 of the block's query rows, quarter tid % 4 of a tile
+    const int srow = tid >> 2, quarter = tid & 3;
+    const int64_t qi = q0 + srow;
+    int bd[KP], bi[KP];
+#pragma unroll
+    for (int p = 0; p < KP; ++p) {
+        bd[p] = 0x7fffffff;
+        bi[p] = 0x7fffffff;
+    }
+    // MFMA role: 16 query rows per wave; lane -> (row lane % 16, k slot lane / 16)
+    const int64_t arow = q0 + wave * 16 + (lane & 15);
+    const int kslot = (lane >> 4) * 16;
+    for (int64_t c0 = c_begin; c0 < c_end; c0 += kUC) {
+        __syncthreads();
+        // stage the candidate tile (16-byte chunks)
+        const int chunks = kUC * dp / 16;
+        for (int e = tid; e < chunks; e += kBlock) {
+            const int r = (e * 16) / dp, off = (e * 16) % dp;
+            const int64_t row = c0 + r;
+            v4i v = {0, 0, 0, 0};
+            if (row < c_end) v = *reinterpret_cast<const v4i*>(Kc + row * dp + off);
+            *reinterpret_cast<v4i*>(Bs + r * dp + off) = v;
+        }
+        __syncthreads();
+        v4i acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = v4i{0, 0, 0, 0};
+        for (int kk = 0; kk < dp; kk += 64) {
+            v4i a = {0, 0, 0, 0};
+            if (arow < n) a = *reinterpret_cast<const v4i*>(Kc + arow * dp + kk + kslot);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const v4i b = *reinterpret_cast<const v4i*>(Bs + (t * 16 + (lane & 15)) * dp + kk +
+                                                            kslot);
+                acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[t], 0, 0, 0);
+            }
+        }
+        // output element (row 4 (lane / 16) + r, column lane % 16) of each 16 x 16 tile
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = wave * 16 + (lane >> 4) * 4 + r;
+                const int col = t * 16 + (lane & 15);
+                Ds[row * kUC + col] = acc[t][r];
+            }
+        }
+        __syncthreads();
+        if (qi < n) {
+            const int nq = nrm[qi];
+            for (int cc = quarter * 16; cc < quarter * 16 + 16; ++cc) {
+                const int64_t j = c0 + cc;
+                if (j >= c_end || j == qi) continue;
+                const int dv = nq + nrm[j] - 2 * Ds[srow * kUC + cc];
+                knn_insert_i<KP>(bd, bi, dv, int(j));
+            }
+        }
+    }
+    if (qi < n) {
+        const int64_t base = ((int64_t(blockIdx.y) * 4 + quarter) * n + qi) * KP;
+#pragma unroll
+        for (int p = 0; p < KP; ++p) {
+            pd[base + p] = bi[p] == 0x7fffffff ? INFINITY : double(bd[p]);
+            pi[base + p] = bi[p];
+        }
+    }
+}
+
 #define HIPCHK(expr)                                                      \
     do {                                                                  \
         hipError_t e_ = (expr);                                           \
@@ -214,6 +352,10 @@ void launch_knn(const double* A, int64_t n, int d, int k, int splits, int64_t cp
 }
 
 }  // namespace
+
+ccm_status knn_finish(DevMem& nbr, DevMem& nd2, int64_t n, int k, double phi, int* src, int* dst,
+                      double* w, int64_t m_cap, int64_t& m_out, double& phi_out, hipStream_t s,
+                      std::string& err);
 
 ccm_status knn_graph(const double* A, int64_t n, int d, int k, double phi, int* src, int* dst,
                      double* w, int64_t m_cap, int64_t& m_out, double& phi_out, hipStream_t s,
@@ -246,6 +388,71 @@ ccm_status knn_graph(const double* A, int64_t n, int d, int k, double phi, int* 
     HIPCHK(hipGetLastError());
     pd.release();
     pi.release();
+    return knn_finish(nbr, nd2, n, k, phi, src, dst, w, m_cap, m_out, phi_out, s, err);
+}
+
+// scale the exact integer distances: d2 = (double)D * scale * scale
+__global__ __launch_bounds__(kBlock) void k_scale_d2(int64_t cnt, double scale,
+                                                     double* __restrict__ d2) {
+    for (int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x; e < cnt;
+         e += int64_t(gridDim.x) * kBlock)
+        d2[e] = d2[e] * scale * scale;
+}
+
+ccm_status knn_graph_u8(const unsigned char* K, int64_t n, int d, double scale, int k, double phi,
+                        int* src, int* dst, double* w, int64_t m_cap, int64_t& m_out,
+                        double& phi_out, hipStream_t s, std::string& err) {
+    const int KP = k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : 32;
+    const int dp = (d + 63) / 64 * 64;
+    DevMem Kc, nrm;
+    HIPCHK(Kc.alloc(size_t(n) * dp, s));
+    HIPCHK(nrm.alloc(size_t(n) * 4, s));
+    hipLaunchKernelGGL(k_u8_prep, dim3(flat_grid(n)), dim3(kBlock), 0, s, K, n, d, dp,
+                       Kc.as<signed char>(), nrm.as<int>());
+    const int64_t qblocks = (n + kUQ - 1) / kUQ;
+    const int64_t ctiles = (n + kUC - 1) / kUC;
+    int64_t splits = (1024 + qblocks - 1) / qblocks;
+    if (splits > ctiles) splits = ctiles;
+    if (splits < 1) splits = 1;
+    const int64_t cps = ((ctiles + splits - 1) / splits) * kUC;
+    splits = (n + cps - 1) / cps;
+    const int64_t cnt = n * k;
+    const int nl = int(splits) * 4;  // partial lists per row
+    DevMem pd, pi, nbr, nd2;
+    HIPCHK(pd.alloc(size_t(nl) * n * KP * 8, s));
+    HIPCHK(pi.alloc(size_t(nl) * n * KP * 4, s));
+    HIPCHK(nbr.alloc(size_t(cnt) * 4, s));
+    HIPCHK(nd2.alloc(size_t(cnt) * 8, s));
+    const size_t lds = size_t(kUC) * dp + size_t(kUQ) * kUC * 4;
+    const dim3 grid{unsigned(qblocks), unsigned(splits), 1u};
+    auto run = [&](auto KPc) {
+        constexpr int kp = decltype(KPc)::value;
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_knn_u8<kp>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        hipLaunchKernelGGL((k_knn_u8<kp>), grid, dim3(kBlock), lds, s, Kc.as<signed char>(),
+                           nrm.as<int>(), n, dp, cps, pd.as<double>(), pi.as<int>());
+        hipLaunchKernelGGL((k_knn_merge<kp>), dim3(flat_grid(n)), dim3(kBlock), 0, s, n, k, nl,
+                           pd.as<double>(), pi.as<int>(), nbr.as<int>(), nd2.as<double>());
+    };
+    switch (KP) {
+        case 4: run(IC<4>{}); break;
+        case 8: run(IC<8>{}); break;
+        case 16: run(IC<16>{}); break;
+        default: run(IC<32>{}); break;
+    }
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_scale_d2, dim3(flat_grid(cnt)), dim3(kBlock), 0, s, cnt, scale,
+                       nd2.as<double>());
+    pd.release();
+    pi.release();
+    return knn_finish(nbr, nd2, n, k, phi, src, dst, w, m_cap, m_out, phi_out, s, err);
+}
+
+// median, union symmetrisation and Gaussian weights of directed k-NN lists
+ccm_status knn_finish(DevMem& nbr, DevMem& nd2, int64_t n, int k, double phi, int* src, int* dst,
+                      double* w, int64_t m_cap, int64_t& m_out, double& phi_out, hipStream_t s,
+                      std::string& err) {
+    const int64_t cnt = n * k;
     // phi = 1 / median of the n k directed distances when not given
     if (!(phi > 0)) {
         DevMem sorted, temp, med;

@@ -181,3 +181,22 @@ def test_l1_ball_projection_tiny_radius(d):
     Pr = ops.project(Y, g * w, np.inf)
     assert np.allclose(P, Pr, rtol=1e-12, atol=1e-14)
     assert np.all(np.abs(P).sum(1) <= g * w * (1 + 1e-12) + 1e-300)
+
+
+@pytest.mark.parametrize("case", ["images", "ties", "ragged"])
+def test_knn_u8_exact_integer_distances(case):
+    torch, ccm = need_gpu()
+    rng = np.random.default_rng(800)
+    if case == "images":
+        A, y, K = synthdata.images784(n_per=150, d=784, n_classes=4)
+    elif case == "ties":
+        K = rng.integers(0, 3, size=(500, 20)).astype(np.uint8)  # massive exact ties
+    else:
+        K = rng.integers(0, 256, size=(333, 70)).astype(np.uint8)
+    scale = 1.0 / 255.0
+    for phi in (0.0, 0.3):
+        src, dst, w, phi_used = ccm.ccm_build_knn_graph_u8(dev(K), scale, 10, phi)
+        s_o, d_o, w_o, phi_o, _, _ = oracle.knn_graph_u8(K, scale, 10, phi if phi > 0 else None)
+        assert phi_used == phi_o
+        assert np.array_equal(host(src), s_o) and np.array_equal(host(dst), d_o)
+        assert np.allclose(host(w), w_o, rtol=1e-14, atol=0)

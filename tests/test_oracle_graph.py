@@ -85,3 +85,16 @@ def test_canonicalize_merges_and_drops():
     s, d, ww = oracle.canonicalize_edges(src, dst, w)
     assert s.tolist() == [0, 1] and d.tolist() == [2, 3]
     assert ww.tolist() == [1.0, 0.75]
+
+
+def test_u8_knn_matches_python_brute_force():
+    rng = np.random.default_rng(5)
+    K = rng.integers(0, 4, size=(40, 6)).astype(np.uint8)  # many ties
+    idx, D = oracle.knn_brute_u8(K, 5)
+    for i in range(K.shape[0]):
+        cand = sorted((int(((K[i].astype(int) - K[j].astype(int)) ** 2).sum()), j)
+                      for j in range(K.shape[0]) if j != i)[:5]
+        assert [j for _, j in cand] == idx[i].tolist()
+        assert [dd for dd, _ in cand] == D[i].tolist()
+    src, dst, w, phi, _, d2 = oracle.knn_graph_u8(K, 0.5, 5)
+    assert np.all(d2 == D * 0.25)
