@@ -138,7 +138,8 @@ ccm_status ccm_build_knn_graph(const double* A, int64_t n, int64_t d, int32_t k,
  * a_i = scale * K_i with K an n x d uint8 array (device), and
  * d^2(i, j) = (double)D_ij * scale * scale with D_ij = sum_k (K_ik - K_jk)^2
  * computed exactly in integer arithmetic (int8 matrix cores with int32
- * accumulation); ties broken by the smaller j.  1 <= d <= 8192.  Other
+ * accumulation); ties broken by the smaller j.  1 <= d <= 2048 (a tile of
+ * 64 candidate rows is held in LDS); CCM_E_INVALID otherwise.  Other
  * arguments, outputs and errors as for ccm_build_knn_graph.
  */
 ccm_status ccm_build_knn_graph_u8(const uint8_t* K, int64_t n, int64_t d, double scale, int32_t k,

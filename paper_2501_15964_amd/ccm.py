@@ -22,6 +22,7 @@ __all__ = [
     "ccm_canonical_edge_count", "ccm_op_gather", "ccm_op_project", "ccm_op_prox",
     "ccm_op_scatter", "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy",
     "ccm_path_vjp", "CCMSolve", "ccm_solve_path_batched", "CcmInstance", "EXPORTED_SYMBOLS",
+    "ccm_build_knn_graph_u8",
 ]
 
 CCM_SSNAL, CCM_ADMM, CCM_AMA = 0, 1, 2

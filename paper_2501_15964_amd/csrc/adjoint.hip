@@ -5,7 +5,8 @@
 //   diag(|c|) (x) I + B_c^T H B_c,  H_l = gamma w_l (I - ghat ghat^T) / ||delta_l||
 // on the edges joining two clusters (delta_l = x_i - x_j, ghat = delta/||delta||).
 // The curvature of edge l is stored in the q = 2 payload layout of the
-// Newton matvec: alpha_l = gamma w_l / ||delta_l|| and the row
+// Newton matvec: per incidence {alpha_l, 1 / r_l} with
+// alpha_l = gamma w_l / ||delta_l|| and r_l = gamma w_l, and the row
 // gamma w_l ghat_l, so that the matvec's a (dl - <Pi, dl> Pi / r^2) is H_l dl.
 #include "launch.hpp"
 
@@ -18,7 +19,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_payload(int64_t m, int d, const 
                                                         const double* __restrict__ w,
                                                         const double* __restrict__ X,
                                                         const int* __restrict__ labels,
-                                                        double gamma, double* __restrict__ alpha,
+                                                        double gamma,
+                                                        const int* __restrict__ epos,
+                                                        double2* __restrict__ ipay,
                                                         double* __restrict__ Pi) {
     const int gl = (threadIdx.x & 63) % LPR;
     constexpr int GPB = kBlock / LPR;
@@ -37,7 +40,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_payload(int64_t m, int d, const 
         const double nd = sqrt(s);
         const bool inter = labels[i] != labels[j] && nd > 0.0;
         const double r = gamma * w[l];
-        if (gl == 0) alpha[l] = inter ? r / nd : 0.0;
+        if (gl == 0) {
+            const double2 v{inter ? r / nd : 0.0, 1.0 / r};
+            ipay[epos[2 * l]] = v;
+            ipay[epos[2 * l + 1]] = v;
+        }
         const double sc = inter ? r / nd : 0.0;
 #pragma unroll
         for (int t = 0; t < NPER; ++t) {
@@ -146,12 +153,12 @@ void launch_label_range(int64_t n, const int* labels, int* range, hipStream_t s)
 }
 
 void launch_adj_payload(const DevGraph& g, int d, const double* X, const int* labels,
-                        double gamma, double* alpha, double* Pi, hipStream_t s) {
+                        double gamma, double2* ipay, double* Pi, hipStream_t s) {
     if (g.m == 0) return;
     dispatch_row(d, [&](auto L, auto N) {
         constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
         hipLaunchKernelGGL((k_adj_payload<lpr, nper>), dim3(row_grid(g.m, lpr)), dim3(kBlock), 0, s,
-                           g.m, d, g.src, g.dst, g.w, X, labels, gamma, alpha, Pi);
+                           g.m, d, g.src, g.dst, g.w, X, labels, gamma, g.epos, ipay, Pi);
     });
 }
 

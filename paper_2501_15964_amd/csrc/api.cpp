@@ -143,7 +143,7 @@ ccm_status ccm_build_knn_graph_u8(const uint8_t* K, int64_t n, int64_t d, double
     g_err.clear();
     if (!K || !src || !dst || !w || !m_out_host) return fail(CCM_E_INVALID, "null argument");
     if (n < 2) return fail(CCM_E_INVALID, "n must be >= 2");
-    if (d < 1 || d > 8192) return fail(CCM_E_INVALID, "need 1 <= d <= 8192");
+    if (d < 1 || d > 2048) return fail(CCM_E_INVALID, "need 1 <= d <= 2048");
     if (n > (int64_t(1) << 30)) return fail(CCM_E_INVALID, "too large");
     if (k < 1 || k > 32 || k > n - 1) return fail(CCM_E_INVALID, "need 1 <= k <= min(n - 1, 32)");
     if (!(scale > 0) || !std::isfinite(scale)) return fail(CCM_E_INVALID, "scale must be > 0");
@@ -443,13 +443,12 @@ ccm_status ccm_op_hess_matvec(const double* X, const double* U, int64_t n, int64
     st = graph_build(src, dst, w, m, n, int(d), true, stream, og, err);
     if (st != CCM_OK) return fail(st, err);
     const int64_t M = m * d;
-    DevMem Pi, al, bi, cn, part;
-    HIPCHK_API(Pi.alloc(size_t(M) * 8, stream));
-    HIPCHK_API(al.alloc(size_t(m) * 8, stream));
-    HIPCHK_API(bi.alloc(size_t(m) * mask_words(int(d)) * 16, stream));
-    HIPCHK_API(cn.alloc(size_t(m) * 4, stream));
+    DevMem Pi, ip, lb, part;
+    HIPCHK_API(Pi.alloc(size_t(std::max<int64_t>(M, 1)) * 8, stream));
+    HIPCHK_API(ip.alloc(size_t(std::max<int64_t>(og.g.nent, 1)) * 16, stream));
+    HIPCHK_API(lb.alloc(size_t(std::max<int64_t>(m, 1)) * lbits_per_edge(int(d)) * 4, stream));
     HIPCHK_API(part.alloc(size_t(kPartialsCap) * 8, stream));
-    Payload pl{al.as<double>(), bi.as<uint64_t>(), cn.as<int>()};
+    Payload pl{ip.as<double2>(), lb.as<uint32_t>()};
     if (m > 0)
         launch_edge_ssnal(og.g, int(d), qk, gamma, sigma, X, U, Pi.as<double>(), pl,
                           part.as<double>(), stream);

@@ -39,17 +39,6 @@ __device__ __forceinline__ int group_sum_i(int v) {
     return v;
 }
 
-// Bits of this lane's row group inside a wave-wide ballot, in lane order.
-template <int LPR>
-__device__ __forceinline__ uint64_t group_bits(uint64_t ballot, int lane) {
-    if constexpr (LPR == 64) {
-        return ballot;
-    } else {
-        const int base = (lane / LPR) * LPR;
-        return (ballot >> base) & ((uint64_t(1) << LPR) - 1);
-    }
-}
-
 // Deterministic block reduction of NV per-thread values; thread v < NV of
 // the block writes the block total of value v to out[v].
 template <int NV>
@@ -73,25 +62,53 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* out)
     }
 }
 
-// Deterministic sum of a partials array (count entries with stride nv,
-// component c), computed identically by every block that calls it.  Uses
-// the whole block; the result is returned to every thread.
-__device__ __forceinline__ double block_sum_partials(const double* partials, int count, int nv,
-                                                     int c) {
-    __shared__ double red[kWaves];
-    double x = 0.0;
-    for (int p = threadIdx.x; p < count; p += blockDim.x) x += partials[p * nv + c];
+// Deterministic sums of K partials arrays (array i: count[i] entries with
+// stride nv[i], starting at ptr[i]), computed identically by every block
+// that calls it: thread t adds entries t, t + blockDim, ... in order, then a
+// fixed xor butterfly inside the wave and the waves in order.  All K sums
+// share one pass of loads and one pair of barriers.  Uses the whole block;
+// the results are returned to every thread.
+template <int K>
+__device__ __forceinline__ void block_sums(const double* const (&ptr)[K], const int (&count)[K],
+                                           const int (&nv)[K], double (&out)[K]) {
+    __shared__ double red[kWaves][K];
+    double x[K];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    for (int i = 0; i < K; ++i) {
+        x[i] = 0.0;
+        for (int p = threadIdx.x; p < count[i]; p += blockDim.x) x[i] += ptr[i][p * nv[i]];
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x[i] += __shfl_xor(x[i], off, 64);
+    }
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     __syncthreads();
-    if (lane == 0) red[wave] = x;
-    __syncthreads();
-    double t = 0.0;
+    if (lane == 0) {
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) t += red[w];
-    return t;
+        for (int i = 0; i < K; ++i) red[wave][i] = x[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) t += red[w][i];
+        out[i] = t;
+    }
+}
+
+// Sum of one partials array (count entries with stride nv, component c).
+__device__ __forceinline__ double block_sum_partials(const double* partials, int count, int nv,
+                                                     int c) {
+    const double* ptr[1] = {partials + c};
+    const int cnt[1] = {count};
+    const int st[1] = {nv};
+    double out[1];
+    block_sums<1>(ptr, cnt, st, out);
+    return out[0];
 }
 
 // Incidence entry of the vertex-major (CSR) layout: e >= 0 means the vertex is

@@ -19,8 +19,9 @@ struct RowProj {
     double pi[NPER];
     double alpha = 1.0;    // q = 2
     int cnt = -1;          // q = inf
-    uint64_t m1[NPER];     // q = 1: |y_k| <= r; q = inf: k in support
-    uint64_t m2[NPER];     // q = inf: y_k < 0
+    uint32_t lm = 0;       // this lane's masks: bit t for coordinate gl + LPR t
+                           // (q = 1: |y_k| <= r; q = inf: k in support),
+                           // bit 16 + t: y_k < 0 (q = inf)
 };
 
 template <int LPR, int NPER, int Q, bool BITS>
@@ -50,7 +51,7 @@ __device__ __forceinline__ void project_row(const double (&y)[NPER], int gl, int
             o.pi[t] = fmin(fmax(y[t], -r), r);
             if constexpr (BITS) {
                 const bool valid = gl + LPR * t < d;
-                o.m1[t] = group_bits<LPR>(__ballot(valid && fabs(y[t]) <= r), lane);
+                if (valid && fabs(y[t]) <= r) o.lm |= 1u << t;
             }
         }
     } else {
@@ -72,14 +73,12 @@ __device__ __forceinline__ void project_row(const double (&y)[NPER], int gl, int
 #pragma unroll
             for (int t = 0; t < NPER; ++t) {
                 o.pi[t] = y[t];
-                if constexpr (BITS) { o.m1[t] = 0; o.m2[t] = 0; }
             }
         } else if (!(r > 0.0)) {
             o.cnt = 0;
 #pragma unroll
             for (int t = 0; t < NPER; ++t) {
                 o.pi[t] = 0.0;
-                if constexpr (BITS) { o.m1[t] = 0; o.m2[t] = 0; }
             }
         } else {
             int cc = group_sum_i<LPR>(c);
@@ -114,8 +113,8 @@ __device__ __forceinline__ void project_row(const double (&y)[NPER], int gl, int
                 o.pi[t] = copysign(mag, y[t]);
                 if constexpr (BITS) {
                     const bool valid = gl + LPR * t < d;
-                    o.m1[t] = group_bits<LPR>(__ballot(valid && v[t] > theta), lane);
-                    o.m2[t] = group_bits<LPR>(__ballot(valid && y[t] < 0.0), lane);
+                    if (valid && v[t] > theta) o.lm |= 1u << t;
+                    if (valid && y[t] < 0.0) o.lm |= 1u << (16 + t);
                 }
             }
         }
@@ -124,21 +123,16 @@ __device__ __forceinline__ void project_row(const double (&y)[NPER], int gl, int
 
 template <int LPR, int NPER, int Q>
 __device__ __forceinline__ void store_payload(const RowProj<LPR, NPER, Q>& o, int64_t l, int gl,
-                                              int d, Payload pl) {
+                                              const int* __restrict__ epos, Payload pl,
+                                              double r) {
+    if constexpr (Q == kQ1 || Q == kQInf) pl.lbits[l * LPR + gl] = o.lm;
     if (gl != 0) return;
-    if constexpr (Q == kQ2) {
-        pl.alpha[l] = o.alpha;
-    } else {
-        const int W = (d + LPR - 1) / LPR;
-        constexpr int NB = (Q == kQ1) ? 1 : 2;
-#pragma unroll
-        for (int t = 0; t < NPER; ++t) {
-            if (t < W) {
-                pl.bits[(l * W + t) * NB] = o.m1[t];
-                if constexpr (Q == kQInf) pl.bits[(l * W + t) * NB + 1] = o.m2[t];
-            }
-        }
-        if constexpr (Q == kQInf) pl.cnt[l] = o.cnt;
+    double2 v;
+    if constexpr (Q == kQ2) v = double2{o.alpha, 1.0 / r};
+    else v = double2{double(o.cnt), 0.0};
+    if constexpr (Q == kQ2 || Q == kQInf) {
+        pl.ipay[epos[2 * l]] = v;
+        pl.ipay[epos[2 * l + 1]] = v;
     }
 }
 
@@ -149,6 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_ssnal(int64_t m, int d, const i
                                                        double sigma, const double* __restrict__ X,
                                                        const double* __restrict__ U,
                                                        double* __restrict__ Pi, Payload pl,
+                                                       const int* __restrict__ epos,
                                                        double* __restrict__ partials) {
     const int lane = threadIdx.x & 63;
     const int gl = lane % LPR;
@@ -185,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_ssnal(int64_t m, int d, const i
                 acc[3] += o.pi[t] * o.pi[t];
             }
         }
-        store_payload<LPR, NPER, Q>(o, l, gl, d, pl);
+        store_payload<LPR, NPER, Q>(o, l, gl, epos, pl, r);
         if (gl == 0) {
             if constexpr (Q == kQ2) acc[4] += (o.alpha < 1.0) ? 1.0 : 0.0;
             else if constexpr (Q == kQInf) acc[4] += (o.cnt >= 0) ? 1.0 : 0.0;
@@ -463,7 +458,8 @@ int launch_edge_ssnal(const DevGraph& g, int d, int qk, double gamma, double sig
         dispatch_q(qk, [&](auto Qc) {
             constexpr int q = decltype(Qc)::value;
             hipLaunchKernelGGL((k_edge_ssnal<lpr, nper, q>), dim3(grid), dim3(kBlock), 0, s, g.m,
-                               d, g.src, g.dst, g.w, gamma, sigma, X, U, Pi, pl, partials);
+                               d, g.src, g.dst, g.w, gamma, sigma, X, U, Pi, pl, g.epos,
+                               partials);
         });
     });
     return grid;

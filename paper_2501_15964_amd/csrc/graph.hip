@@ -97,20 +97,14 @@ __global__ __launch_bounds__(kBlock) void k_inc_ptr(int64_t n, int64_t cnt,
     atomicMax(max_deg, best);
 }
 
-// first vertex of each chunk: the v with inc_ptr[v] <= c C < inc_ptr[v + 1]
-__global__ __launch_bounds__(kBlock) void k_chunk_v(int64_t n, int64_t nchunks, int C,
-                                                    const int* __restrict__ ptr,
-                                                    int* __restrict__ chunk_v) {
-    for (int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x; c < nchunks;
-         c += int64_t(gridDim.x) * kBlock) {
-        const int64_t p = c * C;
-        int64_t lo = 0, hi = n + 1;  // first index with ptr[idx] > p
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (ptr[mid] <= p) lo = mid + 1;
-            else hi = mid;
-        }
-        chunk_v[c] = int(lo - 1);
+// incidence positions of each edge: epos[2 l] (src side), epos[2 l + 1] (dst side)
+__global__ __launch_bounds__(kBlock) void k_epos(int64_t cnt, const Inc* __restrict__ inc,
+                                                 int* __restrict__ epos) {
+    for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < cnt;
+         p += int64_t(gridDim.x) * kBlock) {
+        const int e = inc[p].e;
+        if (e >= 0) epos[2 * int64_t(e)] = int(p);
+        else epos[2 * int64_t(~e) + 1] = int(p);
     }
 }
 
@@ -125,13 +119,14 @@ __global__ __launch_bounds__(kBlock) void k_special_flags(int64_t n, int C,
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_special_emit(int64_t n, const int* __restrict__ flag,
+__global__ __launch_bounds__(kBlock) void k_special_emit(int64_t n, const int* __restrict__ ptr,
+                                                         const int* __restrict__ flag,
                                                          const int* __restrict__ pos,
-                                                         int* __restrict__ special,
+                                                         int4* __restrict__ special,
                                                          int* __restrict__ count) {
     for (int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x; v < n;
          v += int64_t(gridDim.x) * kBlock) {
-        if (flag[v]) special[pos[v]] = int(v);
+        if (flag[v]) special[pos[v]] = int4{int(v), ptr[v], ptr[v + 1], 0};
         if (v == n - 1) count[0] = pos[v] + flag[v];
     }
 }
@@ -239,9 +234,9 @@ ccm_status membership_build(const int* labels, int64_t n, int64_t K, int d, hipS
                             OwnedGraph& out, std::string& err) {
     // rows: clusters; entries: member vertices in ascending order (a stable
     // sort by label keeps vertex order inside each cluster)
-    DevMem key, key_s, val, temp, maxdeg;
+    DevMem key, val, temp, maxdeg;
     HIPCHK(key.alloc(size_t(n) * 4, s));
-    HIPCHK(key_s.alloc(size_t(n) * 4, s));
+    HIPCHK(out.irow.alloc(size_t(n) * 4, s));
     HIPCHK(val.alloc(size_t(n) * 8, s));
     HIPCHK(out.inc.alloc(size_t(n) * 8, s));
     HIPCHK(out.inc_ptr.alloc(size_t(K + 1) * 4, s));
@@ -251,20 +246,21 @@ ccm_status membership_build(const int* labels, int64_t n, int64_t K, int d, hipS
                        key.as<int>(), val.as<Inc>());
     size_t b = 0;
     const int nb = bits_for(K);
-    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, b, key.as<int>(), key_s.as<int>(),
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, b, key.as<int>(), out.irow.as<int>(),
                                               val.as<unsigned long long>(),
                                               out.inc.as<unsigned long long>(), int(n), 0, nb, s));
     HIPCHK(temp.alloc(b, s));
-    HIPCHK(hipcub::DeviceRadixSort::SortPairs(temp.p, b, key.as<int>(), key_s.as<int>(),
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(temp.p, b, key.as<int>(), out.irow.as<int>(),
                                               val.as<unsigned long long>(),
                                               out.inc.as<unsigned long long>(), int(n), 0, nb, s));
     hipLaunchKernelGGL(k_inc_ptr, dim3(flat_grid(K + 1)), dim3(kBlock), 0, s, K, n,
-                       key_s.as<int>(), out.inc_ptr.as<int>(), maxdeg.as<int>());
+                       out.irow.as<int>(), out.inc_ptr.as<int>(), maxdeg.as<int>());
     out.g.n = K;
     out.g.m = 0;
     out.g.nent = n;
     out.g.inc_ptr = out.inc_ptr.as<int>();
     out.g.inc = out.inc.as<Inc>();
+    out.g.irow = out.irow.as<int>();
     return build_chunks(d, s, out, err);
 }
 
@@ -312,10 +308,11 @@ ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t 
     // vertex-major incidence lists: entries (vertex, edge) sorted stably by
     // vertex keep each list in ascending edge order
     const int64_t cnt = 2 * mc;
-    DevMem vk, vk_s, vv, temp, maxdeg;
+    DevMem vk, vv, temp, maxdeg;
     HIPCHK(vk.alloc(cnt * 4, s));
-    HIPCHK(vk_s.alloc(cnt * 4, s));
     HIPCHK(vv.alloc(cnt * 8, s));
+    HIPCHK(out.irow.alloc(std::max<int64_t>(cnt, 1) * 4, s));
+    HIPCHK(out.epos.alloc(std::max<int64_t>(cnt, 1) * 4, s));
     HIPCHK(out.inc.alloc(cnt * 8, s));
     HIPCHK(out.inc_ptr.alloc((n + 1) * 4, s));
     HIPCHK(maxdeg.alloc(4, s));
@@ -326,20 +323,24 @@ ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t 
         size_t b = 0;
         const int nb = bits_for(n);
         HIPCHK(hipcub::DeviceRadixSort::SortPairs(
-            nullptr, b, vk.as<int>(), vk_s.as<int>(), vv.as<unsigned long long>(),
+            nullptr, b, vk.as<int>(), out.irow.as<int>(), vv.as<unsigned long long>(),
             out.inc.as<unsigned long long>(), int(cnt), 0, nb, s));
         HIPCHK(temp.alloc(b, s));
         HIPCHK(hipcub::DeviceRadixSort::SortPairs(
-            temp.p, b, vk.as<int>(), vk_s.as<int>(), vv.as<unsigned long long>(),
+            temp.p, b, vk.as<int>(), out.irow.as<int>(), vv.as<unsigned long long>(),
             out.inc.as<unsigned long long>(), int(cnt), 0, nb, s));
+        hipLaunchKernelGGL(k_epos, dim3(flat_grid(cnt)), dim3(kBlock), 0, s, cnt,
+                           out.inc.as<Inc>(), out.epos.as<int>());
     }
     hipLaunchKernelGGL(k_inc_ptr, dim3(flat_grid(n + 1)), dim3(kBlock), 0, s, n, cnt,
-                       vk_s.as<int>(), out.inc_ptr.as<int>(), maxdeg.as<int>());
+                       out.irow.as<int>(), out.inc_ptr.as<int>(), maxdeg.as<int>());
     int md = 0;
     HIPCHK(hipMemcpyAsync(&md, maxdeg.p, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     out.g.inc_ptr = out.inc_ptr.as<int>();
     out.g.inc = out.inc.as<Inc>();
+    out.g.irow = out.irow.as<int>();
+    out.g.epos = out.epos.as<int>();
     out.g.max_deg = md;
     out.g.nent = cnt;
     return build_chunks(d, s, out, err);
@@ -349,16 +350,16 @@ ccm_status build_chunks(int d, hipStream_t s, OwnedGraph& out, std::string& err)
     // balanced chunks of the incidence array and the fix-up vertex list
     const int64_t n = out.g.n;
     const int64_t cnt = out.g.nent;
+    if (cnt > 0 && (!out.g.inc || !out.g.irow || !out.g.inc_ptr)) {
+        err = "internal: incidence lists incomplete (entries, vertex ids or offsets missing)";
+        return CCM_E_HIP;
+    }
     const int C = chunk_for(d);
     const int64_t nch = (cnt + C - 1) / C;
     out.g.chunk = C;
     out.g.nchunks = nch;
-    HIPCHK(out.chunk_v.alloc(size_t(std::max<int64_t>(nch, 1)) * 4, s));
-    HIPCHK(out.special.alloc(size_t(n) * 4, s));
+    HIPCHK(out.special.alloc(size_t(n) * 16, s));
     HIPCHK(out.carry.alloc(size_t(std::max<int64_t>(nch, 1)) * 2 * 2 * size_t(d) * 8, s));
-    if (nch > 0)
-        hipLaunchKernelGGL(k_chunk_v, dim3(flat_grid(nch)), dim3(kBlock), 0, s, n, nch, C,
-                           out.g.inc_ptr, out.chunk_v.as<int>());
     {
         DevMem flag, pos, temp2, count;
         HIPCHK(flag.alloc(size_t(n) * 4, s));
@@ -373,14 +374,14 @@ ccm_status build_chunks(int d, hipStream_t s, OwnedGraph& out, std::string& err)
         HIPCHK(hipcub::DeviceScan::ExclusiveSum(temp2.p, b, flag.as<int>(), pos.as<int>(), int(n),
                                                 s));
         hipLaunchKernelGGL(k_special_emit, dim3(flat_grid(n)), dim3(kBlock), 0, s, n,
-                           flag.as<int>(), pos.as<int>(), out.special.as<int>(), count.as<int>());
+                           out.g.inc_ptr, flag.as<int>(), pos.as<int>(), out.special.as<int4>(),
+                           count.as<int>());
         int ns = 0;
         HIPCHK(hipMemcpyAsync(&ns, count.p, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         out.g.nspecial = ns;
     }
-    out.g.chunk_v = out.chunk_v.as<int>();
-    out.g.special = out.special.as<int>();
+    out.g.special = out.special.as<int4>();
     out.g.carry = out.carry.as<double>();
     return CCM_OK;
 }

@@ -63,18 +63,21 @@ inline int flat_grid(int64_t count) {
     return int(g);
 }
 
-// 64-bit payload words per edge for the bit masks of the q = 1 / q = inf
-// generalized Jacobians (one word per row slice t).
-inline int mask_words(int d) {
-    const int lpr = lanes_per_row(d);
-    return (d + lpr - 1) / lpr;
-}
+// 32-bit mask words per edge of the q = 1 / q = inf Jacobian payload: one per
+// lane of a row group.
+inline int lbits_per_edge(int d) { return lanes_per_row(d); }
 
-// Per-edge generalized-Jacobian payload written by the SSNAL edge pass.
+// Per-edge generalized-Jacobian payload written by the SSNAL edge pass.  The
+// scalar part is stored once per incidence entry (both incidences of an edge
+// hold the same value), so a vertex kernel reads it at the entry's position
+// together with the entry itself instead of through the edge index.
 struct Payload {
-    double* alpha = nullptr;   // q = 2: r/||y|| outside the ball, 1 inside
-    uint64_t* bits = nullptr;  // q = 1: in-box mask; q = inf: support and sign masks
-    int* cnt = nullptr;        // q = inf: -1 inside the ball, else support size
+    double2* ipay = nullptr;   // per incidence: q = 2 {a, 1/r} with a = r/||y||
+                               // outside the ball, 1 inside; q = inf {cnt, 0},
+                               // cnt = -1 inside the ball, else support size
+    uint32_t* lbits = nullptr; // per edge and lane (m x LPR): bit t = mask of
+                               // coordinate gl + LPR t (q = 1: |y_k| <= r;
+                               // q = inf: k in support), bit 16 + t: y_k < 0
 };
 
 struct DevGraph {
@@ -84,17 +87,19 @@ struct DevGraph {
     const double* w = nullptr;
     const int* inc_ptr = nullptr;  // n + 1
     const Inc* inc = nullptr;      // 2 m
+    const int* irow = nullptr;     // vertex of each incidence entry (2 m)
+    const int* epos = nullptr;     // incidence positions of edge l: [2 l] at src, [2 l + 1] at dst
     int max_deg = 0;
     // Balanced split of the incidence array for the vertex kernels: chunk c
     // holds incidences [c C, (c + 1) C).  A vertex whose incidence range lies
     // inside one chunk is finished by that chunk; a vertex cut by a chunk
-    // boundary leaves one partial row per chunk in `carry`, summed in chunk
+    // boundary leaves one partial row per chunk in `carry` (slot 0 when the
+    // chunk starts inside the vertex's range, else slot 1), summed in chunk
     // order by a fix-up pass that also handles isolated vertices.
     int64_t nent = 0;               // incidence entries (2 m for an edge graph)
     int chunk = 16;                 // C
     int64_t nchunks = 0;
-    const int* chunk_v = nullptr;   // vertex owning the first incidence of each chunk
-    const int* special = nullptr;   // vertices finished by the fix-up pass
+    const int4* special = nullptr;  // fix-up vertices {v, inc_ptr[v], inc_ptr[v + 1], 0}
     int64_t nspecial = 0;
     double* carry = nullptr;        // nchunks x 2 slots x (2 d) doubles
 };
@@ -192,7 +197,7 @@ int cg_update_grid(int64_t N);
 constexpr int kAxpyNV = 2;
 int launch_trial(int64_t N, const double* X, const double* D, double alpha, const double* A,
                  const double* G, double* Xt, double* partials, hipStream_t s);
-// sum partials[p * nv + c] over p for every c; out[c] = total.
+// sum partials[p * nv + c] over p for every c < nv (1 <= nv <= 7); out[c] = total.
 void launch_finalize(const double* partials, int nparts, int nv, double* out, hipStream_t s);
 void launch_fill(double* x, int64_t N, double v, hipStream_t s);
 // x += alpha y
@@ -233,9 +238,10 @@ void launch_segsum(const double* rows, int nv, const int64_t* seg, int nseg, dou
 
 // ---- adjoint (adjoint.hip) ----------------------------------------------------
 // Per edge: delta = x_i - x_j; for an edge joining two clusters
-// alpha = gamma w / ||delta|| and Pi = gamma w delta / ||delta||, else alpha = 0.
+// alpha = gamma w / ||delta|| and Pi = gamma w delta / ||delta||, else alpha = 0;
+// ipay (per incidence, q = 2 payload layout) = {alpha, 1 / (gamma w)}.
 void launch_adj_payload(const DevGraph& g, int d, const double* X, const int* labels,
-                        double gamma, double* alpha, double* Pi, hipStream_t s);
+                        double gamma, double2* ipay, double* Pi, hipStream_t s);
 // v[i, :] = lam[labels[i], :]
 void launch_expand(int64_t n, int d, const int* labels, const double* lam, double* v,
                    hipStream_t s);

@@ -157,7 +157,7 @@ struct Solver::Impl {
     DevMem cgx, cgr, cgu, cgw, cgp, cgs;
     // edge buffers
     DevMem bU, bPi, bPit, bZ, bL, bQ, bZold;
-    DevMem al0, al1, bi0, bi1, cn0, cn1;
+    DevMem ip0, ip1, lb0, lb1;  // Jacobian payload (current, trial)
     DevMem fused, parent, rank, ltemp;
     size_t ltemp_bytes = 0;
     // reductions
@@ -209,18 +209,15 @@ struct Solver::Impl {
         if (o.method == CCM_SSNAL) {
             HIPCHK(bPi.alloc(eb, s));
             HIPCHK(bPit.alloc(eb, s));
-            const int W = mask_words(d);
-            if (qk == kQ2) {
-                HIPCHK(al0.alloc(m * 8, s));
-                HIPCHK(al1.alloc(m * 8, s));
-            } else {
-                const int NB = qk == kQ1 ? 1 : 2;
-                HIPCHK(bi0.alloc(size_t(m) * W * NB * 8, s));
-                HIPCHK(bi1.alloc(size_t(m) * W * NB * 8, s));
-                if (qk == kQInf) {
-                    HIPCHK(cn0.alloc(m * 4, s));
-                    HIPCHK(cn1.alloc(m * 4, s));
-                }
+            const size_t ne = size_t(std::max<int64_t>(g.nent, 1));
+            if (qk != kQ1) {
+                HIPCHK(ip0.alloc(ne * 16, s));
+                HIPCHK(ip1.alloc(ne * 16, s));
+            }
+            if (qk != kQ2) {
+                const size_t lw = size_t(std::max<int64_t>(m, 1)) * lbits_per_edge(d);
+                HIPCHK(lb0.alloc(lw * 4, s));
+                HIPCHK(lb1.alloc(lw * 4, s));
             }
         } else if (o.method == CCM_ADMM) {
             HIPCHK(bZ.alloc(eb, s));
@@ -255,8 +252,8 @@ struct Solver::Impl {
         U = bU.as<double>();
         Pi = bPi.as<double>();
         Pit = bPit.as<double>();
-        pl = Payload{al0.as<double>(), bi0.as<uint64_t>(), cn0.as<int>()};
-        plt = Payload{al1.as<double>(), bi1.as<uint64_t>(), cn1.as<int>()};
+        pl = Payload{ip0.as<double2>(), lb0.as<uint32_t>()};
+        plt = Payload{ip1.as<double2>(), lb1.as<uint32_t>()};
         cg.x = cgx.as<double>();
         cg.r = cgr.as<double>();
         cg.u = cgu.as<double>();
@@ -346,17 +343,19 @@ struct Solver::Impl {
     }
 
     double lap_bytes() const {
-        // ADMM matrix I + sigma B^T B: vectors and incidence lists only
-        return 16.0 * double(N) + 4.0 * double(n + 1) + 16.0 * double(m);
+        // ADMM matrix I + sigma B^T B: read V, write out, incidence entries
+        // and their vertex ids
+        return 16.0 * double(N) + 12.0 * double(g.nent);
     }
     double matvec_bytes(double nout) const {
         // one-pass minimum traffic of a Newton matvec launch: read V, write
-        // out, incidence lists, and the per-edge payload (rows of Pi only for
-        // edges whose Jacobian is not the identity)
-        double b = 16.0 * double(N) + 4.0 * double(n + 1) + 16.0 * double(m);
-        if (qk == kQ2) b += 8.0 * double(m) + nout * (8.0 * d + 8.0);
-        else if (qk == kQ1) b += double(m) * mask_words(d) * 8.0;
-        else b += 4.0 * double(m) + nout * mask_words(d) * 16.0;
+        // out, the incidence entries with their vertex ids, and the Jacobian
+        // payload: per-incidence scalars, lane masks, and the rows of Pi of
+        // the edges whose Jacobian is not the identity (q = 2)
+        double b = 16.0 * double(N) + 12.0 * double(g.nent);
+        if (qk == kQ2) b += 16.0 * double(g.nent) + nout * 8.0 * d;
+        else if (qk == kQ1) b += double(m) * lbits_per_edge(d) * 4.0;
+        else b += 16.0 * double(g.nent) + nout * lbits_per_edge(d) * 4.0;
         return b;
     }
 

@@ -49,7 +49,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(
     double* __restrict__ state, int* flag, double thr) {
     if (flag[0]) return;
     const int par = j & 1;
-    const double rr = block_sum_partials(upd_prev, nparts_upd, 2, 1);
+    // r.r (stop test), gamma = r.u, delta = w.u in one pass
+    const double* ptr[3] = {upd_prev + 1, upd_prev, wu};
+    const int cnt[3] = {nparts_upd, nparts_upd, nparts_mv};
+    const int st[3] = {2, 2, 1};
+    double sums[3];
+    block_sums<3>(ptr, cnt, st, sums);
+    const double rr = sums[0], gam = sums[1], del = sums[2];
     if (rr <= thr) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             flag[0] = 1;
@@ -57,8 +63,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(
         }
         return;
     }
-    const double gam = block_sum_partials(upd_prev, nparts_upd, 2, 0);
-    const double del = block_sum_partials(wu, nparts_mv, 1, 0);
     double alpha, beta;
     if (j == 0) {
         beta = 0.0;
@@ -118,11 +122,23 @@ __global__ __launch_bounds__(kBlock) void k_trial(int64_t N, const double* __res
     block_reduce_store<kAxpyNV>(acc, partials + blockIdx.x * kAxpyNV);
 }
 
+template <int NV>
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials,
-                                                     int nparts, int nv, double* __restrict__ out) {
-    for (int c = 0; c < nv; ++c) {
-        const double t = block_sum_partials(partials, nparts, nv, c);
-        if (threadIdx.x == 0) out[c] = t;
+                                                     int nparts, double* __restrict__ out) {
+    const double* ptr[NV];
+    int cnt[NV], st[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        ptr[c] = partials + c;
+        cnt[c] = nparts;
+        st[c] = NV;
+    }
+    double t[NV];
+    block_sums<NV>(ptr, cnt, st, t);
+    if (threadIdx.x < NV) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c)
+            if (threadIdx.x == c) out[c] = t[c];
     }
 }
 
@@ -367,7 +383,15 @@ int launch_trial(int64_t N, const double* X, const double* D, double alpha, cons
 }
 
 void launch_finalize(const double* partials, int nparts, int nv, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, partials, nparts, nv, out);
+    switch (nv) {
+        case 1: hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kBlock), 0, s, partials, nparts, out); break;
+        case 2: hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kBlock), 0, s, partials, nparts, out); break;
+        case 3: hipLaunchKernelGGL(k_finalize<3>, dim3(1), dim3(kBlock), 0, s, partials, nparts, out); break;
+        case 4: hipLaunchKernelGGL(k_finalize<4>, dim3(1), dim3(kBlock), 0, s, partials, nparts, out); break;
+        case 5: hipLaunchKernelGGL(k_finalize<5>, dim3(1), dim3(kBlock), 0, s, partials, nparts, out); break;
+        case 6: hipLaunchKernelGGL(k_finalize<6>, dim3(1), dim3(kBlock), 0, s, partials, nparts, out); break;
+        default: hipLaunchKernelGGL(k_finalize<7>, dim3(1), dim3(kBlock), 0, s, partials, nparts, out); break;
+    }
 }
 
 void launch_fill(double* x, int64_t N, double v, hipStream_t s) {

@@ -1,130 +1,97 @@
 // Vertex-centric kernels: the transposed operator B^T (a signed sum of edge
 // rows into vertex rows) and the SSNAL Newton matvec V + sigma B^T P B V.
 //
-// Both read the vertex-major incidence lists (CSR by vertex, entries in
-// ascending edge order).  k-NN graphs are skewed (a few hub vertices have
-// tens of times the mean degree), so work is not split by vertex but by
-// equal chunks of C incidences: a row group takes one chunk, finishes every
-// vertex whose incidences all lie inside it, and leaves a partial row for a
-// vertex cut by a chunk boundary.  A fix-up pass sums those partials in
-// chunk order and finishes isolated vertices.  There are no atomics and the
-// summation order is fixed, so results are bit-reproducible.  An edge row is
-// read by both of its endpoints.
+// Both walk the vertex-major incidence array (entries sorted by vertex, each
+// vertex's entries in ascending edge order).  k-NN graphs are skewed (a few
+// hub vertices have tens of times the mean degree), so work is not split by
+// vertex but by equal chunks of C incidences: a row group takes one chunk,
+// finishes every vertex whose incidences all lie inside it, and leaves a
+// partial row for a vertex cut by a chunk boundary.  A fix-up pass sums those
+// partials in chunk order and finishes isolated vertices.  There are no
+// atomics and the summation order is fixed, so results are bit-reproducible.
+// An edge row is read by both of its endpoints.
+//
+// Everything needed to issue an entry's row gathers (edge, other endpoint,
+// the entry's own vertex, the Jacobian scalars) is stored at the entry's
+// position, so a batch of U entries costs one round of independent index
+// loads and then one round of row loads; vertex boundaries are read off the
+// per-entry vertex ids, and the chunk's neighbours irow[cs - 1], irow[ce]
+// tell whether its first and last vertices are cut.
 #include "launch.hpp"
 
 namespace ccm {
 namespace {
 
-template <int LPR>
-__device__ __forceinline__ bool mask_bit(const uint64_t* bits, int64_t l, int W, int NB, int t,
-                                         int b, int gl) {
-    return (bits[(l * W + t) * NB + b] >> gl) & 1u;
-}
-
-// Incidences are processed U at a time: the U incidence entries are loaded
-// together, then every row they point at.
+// entries per batch: the batch's rows are gathered together.  Short rows
+// are latency-bound, so their kernels also gather the next vertex's own rows
+// with the batch; long rows are bandwidth-bound and keep registers for
+// occupancy instead.
 template <int NPER>
 struct Unroll {
-    static constexpr int U = NPER <= 2 ? 8 : NPER == 4 ? 4 : 2;
+    static constexpr int U = NPER <= 2 ? 8 : NPER == 4 ? 4 : NPER == 8 ? 2 : 1;   // matvec
+    static constexpr int US = NPER <= 2 ? 8 : NPER == 4 ? 4 : NPER == 8 ? 2 : 1;  // scatter
+    static constexpr bool PREFETCH = NPER <= 4;
 };
 
-// Per-incidence data of the generalized Jacobian (q = 2: a = r/||y|| outside
-// the ball or 1 inside; outside, f = a / r^2 and ir = 1 / r; q = inf: support
-// size, -1 inside).
+// Per-incidence data.  q = 2: a = r/||y|| outside the ball, 1 inside; ir = 1/r
+// and f = a / r^2 where the Jacobian is a (I - yhat yhat^T); q = inf: support
+// size, -1 inside.
 struct Meta {
-    int64_t l;
-    int64_t o;
+    int l, o, v;
     bool pos;
-    double a, f, ir;
+    double a, ir, f;
     int cnt;
 };
 
 template <int Q, bool PAY, bool ADJ = false>
-__device__ __forceinline__ Meta load_meta(const Inc* __restrict__ inc, int64_t p,
-                                          const Payload& pl, const double* __restrict__ w,
-                                          double gamma) {
-    const Inc e = inc[p];
+__device__ __forceinline__ Meta load_meta(const DevGraph& g, int64_t p, const Payload& pl) {
+    const Inc e = g.inc[p];
     Meta m;
     m.pos = e.e >= 0;
     m.l = m.pos ? e.e : ~e.e;
     m.o = e.o;
+    m.v = g.irow[p];
     m.a = 1.0;
-    m.f = 0.0;
     m.ir = 0.0;
+    m.f = 0.0;
     m.cnt = -1;
     if constexpr (PAY && Q == kQ2) {
-        m.a = pl.alpha[m.l];
-        if ((ADJ || m.a < 1.0) && m.a > 0.0) {
-            const double r = gamma * w[m.l];
-            m.ir = 1.0 / r;
-            m.f = m.a * m.ir * m.ir;
-        }
+        const double2 q = pl.ipay[p];
+        m.a = q.x;
+        m.ir = q.y;
+        if ((ADJ || m.a < 1.0) && m.a > 0.0) m.f = m.a * m.ir * m.ir;
     } else if constexpr (PAY && Q == kQInf) {
-        m.cnt = pl.cnt[m.l];
+        m.cnt = int(pl.ipay[p].x);
     }
     return m;
 }
 
-// ---- B^T Z (and the Jacobi diagonal of I + sigma B^T P B) -------------------
+struct ChunkCtx {
+    int64_t cs, ce;      // incidence range of the chunk
+    int64_t vprev;       // vertex of entry cs - 1 (-1 if none)
+    int64_t vnext;       // vertex of entry ce (-1 if none)
+};
 
-template <int LPR, int NPER, int Q, bool DIAG>
-__device__ __forceinline__ void scatter_range(int64_t pa, int64_t pb, int d, int gl, int W,
-                                              const Inc* __restrict__ inc,
-                                              const double* __restrict__ Z, const Payload& pl,
-                                              const double* __restrict__ w, double gamma,
-                                              double (&acc)[NPER], double (&dg)[NPER]) {
-    constexpr int U = Unroll<NPER>::U;
-    for (int64_t p0 = pa; p0 < pb; p0 += U) {
-        Meta mt[U];
-        double zr[U][NPER];
+__device__ __forceinline__ ChunkCtx chunk_ctx(const DevGraph& g, int64_t c) {
+    ChunkCtx x;
+    x.cs = c * g.chunk;
+    x.ce = x.cs + g.chunk < g.nent ? x.cs + g.chunk : g.nent;
+    x.vprev = x.cs > 0 ? g.irow[x.cs - 1] : -1;
+    x.vnext = x.ce < g.nent ? g.irow[x.ce] : -1;
+    return x;
+}
+
+template <int LPR, int NPER>
+__device__ __forceinline__ void load_row(const double* __restrict__ V, int64_t v, int d, int gl,
+                                         double (&r)[NPER]) {
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (p0 + u < pb) mt[u] = load_meta<Q, DIAG>(inc, p0 + u, pl, w, gamma);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-#pragma unroll
-            for (int t = 0; t < NPER; ++t) {
-                const int k = gl + LPR * t;
-                zr[u][t] = (p0 + u < pb && k < d) ? Z[mt[u].l * d + k] : 0.0;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (p0 + u >= pb) break;
-            const Meta& m = mt[u];
-#pragma unroll
-            for (int t = 0; t < NPER; ++t) acc[t] += m.pos ? zr[u][t] : -zr[u][t];
-            if constexpr (DIAG) {
-                if constexpr (Q == kQ2) {
-                    if (m.a >= 1.0) {
-#pragma unroll
-                        for (int t = 0; t < NPER; ++t) dg[t] += 1.0;
-                    } else if (m.a > 0.0) {
-#pragma unroll
-                        for (int t = 0; t < NPER; ++t) {
-                            const double yh = zr[u][t] * m.ir;
-                            dg[t] += m.a * (1.0 - yh * yh);
-                        }
-                    }
-                } else if constexpr (Q == kQ1) {
-#pragma unroll
-                    for (int t = 0; t < NPER; ++t)
-                        if (t < W && mask_bit<LPR>(pl.bits, m.l, W, 1, t, 0, gl)) dg[t] += 1.0;
-                } else {
-                    if (m.cnt < 0) {
-#pragma unroll
-                        for (int t = 0; t < NPER; ++t) dg[t] += 1.0;
-                    } else if (m.cnt > 0) {
-                        const double f = 1.0 - 1.0 / double(m.cnt);
-#pragma unroll
-                        for (int t = 0; t < NPER; ++t)
-                            if (t < W && mask_bit<LPR>(pl.bits, m.l, W, 2, t, 0, gl)) dg[t] += f;
-                    }
-                }
-            }
-        }
+    for (int t = 0; t < NPER; ++t) {
+        const int k = gl + LPR * t;
+        r[t] = (V && k < d) ? V[v * d + k] : 0.0;
     }
 }
+
+// ---- B^T Z (and the Jacobi diagonal of I + sigma B^T P B) -------------------
 
 struct ScatterOut {
     double cx, ca, cz, sigma;
@@ -137,6 +104,7 @@ struct ScatterOut {
 
 template <int LPR, int NPER, bool DIAG>
 __device__ __forceinline__ void scatter_finish(int64_t v, int d, int gl, const ScatterOut& so,
+                                               const double (&xr)[NPER], const double (&ar)[NPER],
                                                const double (&acc)[NPER], const double (&dg)[NPER],
                                                double (&acc4)[kScatterNV]) {
     double r4[kScatterNV] = {0.0, 0.0, 0.0, 0.0};
@@ -144,14 +112,12 @@ __device__ __forceinline__ void scatter_finish(int64_t v, int d, int gl, const S
     for (int t = 0; t < NPER; ++t) {
         const int k = gl + LPR * t;
         if (k < d) {
-            const double xv = so.X ? so.X[v * d + k] : 0.0;
-            const double av = so.A ? so.A[v * d + k] : 0.0;
-            const double o = so.cx * xv + so.ca * av + so.cz * acc[t];
+            const double o = so.cx * xr[t] + so.ca * ar[t] + so.cz * acc[t];
             so.out[v * d + k] = o;
-            const double dx = xv - av;
+            const double dx = xr[t] - ar[t];
             r4[0] += o * o;
             r4[1] += 0.5 * dx * dx;
-            r4[2] += av * acc[t];
+            r4[2] += ar[t] * acc[t];
             r4[3] += acc[t] * acc[t];
             if constexpr (DIAG) so.Dinv[v * d + k] = 1.0 / (1.0 + so.sigma * dg[t]);
         }
@@ -170,31 +136,30 @@ __device__ __forceinline__ void scatter_finish(int64_t v, int d, int gl, const S
 template <int LPR, int NPER, int Q, bool DIAG>
 __global__ __launch_bounds__(kBlock) void k_scatter_chunk(DevGraph g, int d, ScatterOut so,
                                                           const double* __restrict__ Z, Payload pl,
-                                                          double gamma,
                                                           double* __restrict__ partials) {
+    constexpr int U = Unroll<NPER>::US;
     const int gl = (threadIdx.x & 63) % LPR;
     constexpr int GPB = kBlock / LPR;
-    const int W = (d + LPR - 1) / LPR;
-    const int64_t T = g.nent;
-    const int C = g.chunk;
     const int CW = 2 * d;
     double acc4[kScatterNV] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t c = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; c < g.nchunks;
          c += int64_t(gridDim.x) * GPB) {
-        const int64_t cs = c * C;
-        const int64_t ce = cs + C < T ? cs + C : T;
-        int64_t v = g.chunk_v[c];
-        int64_t p = cs;
+        const ChunkCtx cx = chunk_ctx(g, c);
+        int64_t vcur = -1;
         bool first = true;
-        while (p < ce) {
-            const int64_t vb = g.inc_ptr[v], ve = g.inc_ptr[v + 1];
-            const int64_t se = ve < ce ? ve : ce;
-            double acc[NPER], dg[NPER];
+        double acc[NPER], dg[NPER], xr[NPER], ar[NPER];
 #pragma unroll
-            for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = 0.0;
-            scatter_range<LPR, NPER, Q, DIAG>(p, se, d, gl, W, g.inc, Z, pl, g.w, gamma, acc, dg);
-            if (vb >= cs && ve <= ce) {
-                scatter_finish<LPR, NPER, DIAG>(v, d, gl, so, acc, dg, acc4);
+        for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = xr[t] = ar[t] = 0.0;
+        auto flush = [&](bool cut) {
+            if (!cut) {
+                if constexpr (!Unroll<NPER>::PREFETCH) {
+                    double x2[NPER], a2[NPER];
+                    load_row<LPR, NPER>(so.X, vcur, d, gl, x2);
+                    load_row<LPR, NPER>(so.A, vcur, d, gl, a2);
+                    scatter_finish<LPR, NPER, DIAG>(vcur, d, gl, so, x2, a2, acc, dg, acc4);
+                } else {
+                    scatter_finish<LPR, NPER, DIAG>(vcur, d, gl, so, xr, ar, acc, dg, acc4);
+                }
             } else {
                 double* cr = g.carry + (c * 2 + (first ? 0 : 1)) * CW;
 #pragma unroll
@@ -206,13 +171,76 @@ __global__ __launch_bounds__(kBlock) void k_scatter_chunk(DevGraph g, int d, Sca
                     }
                 }
             }
-            p = se;
-            first = false;
-            if (p < ce) {
-                ++v;
-                while (g.inc_ptr[v + 1] <= p) ++v;  // skip isolated vertices
+        };
+        for (int64_t p0 = cx.cs; p0 < cx.ce; p0 += U) {
+            Meta mt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (p0 + u < cx.ce) mt[u] = load_meta<Q, DIAG>(g, p0 + u, pl);
+            double zr[U][NPER];
+            uint32_t lb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = p0 + u < cx.ce;
+#pragma unroll
+                for (int t = 0; t < NPER; ++t) {
+                    const int k = gl + LPR * t;
+                    zr[u][t] = (ok && k < d) ? Z[int64_t(mt[u].l) * d + k] : 0.0;
+                }
+                lb[u] = 0u;
+                if constexpr (DIAG && Q != kQ2)
+                    if (ok) lb[u] = pl.lbits[int64_t(mt[u].l) * LPR + gl];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (p0 + u >= cx.ce) break;
+                const Meta& m = mt[u];
+                if (m.v != vcur) {
+                    if (vcur >= 0) {
+                        flush(first && vcur == cx.vprev);
+                        first = false;
+                    }
+                    vcur = m.v;
+                    if constexpr (Unroll<NPER>::PREFETCH) {
+                        load_row<LPR, NPER>(so.X, vcur, d, gl, xr);
+                        load_row<LPR, NPER>(so.A, vcur, d, gl, ar);
+                    }
+#pragma unroll
+                    for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = 0.0;
+                }
+#pragma unroll
+                for (int t = 0; t < NPER; ++t) acc[t] += m.pos ? zr[u][t] : -zr[u][t];
+                if constexpr (DIAG) {
+                    if constexpr (Q == kQ2) {
+                        if (m.a >= 1.0) {
+#pragma unroll
+                            for (int t = 0; t < NPER; ++t) dg[t] += 1.0;
+                        } else if (m.a > 0.0) {
+#pragma unroll
+                            for (int t = 0; t < NPER; ++t) {
+                                const double yh = zr[u][t] * m.ir;
+                                dg[t] += m.a * (1.0 - yh * yh);
+                            }
+                        }
+                    } else if constexpr (Q == kQ1) {
+#pragma unroll
+                        for (int t = 0; t < NPER; ++t)
+                            if ((lb[u] >> t) & 1u) dg[t] += 1.0;
+                    } else {
+                        if (m.cnt < 0) {
+#pragma unroll
+                            for (int t = 0; t < NPER; ++t) dg[t] += 1.0;
+                        } else if (m.cnt > 0) {
+                            const double f = 1.0 - 1.0 / double(m.cnt);
+#pragma unroll
+                            for (int t = 0; t < NPER; ++t)
+                                if ((lb[u] >> t) & 1u) dg[t] += f;
+                        }
+                    }
+                }
             }
         }
+        if (vcur >= 0) flush((first && vcur == cx.vprev) || vcur == cx.vnext);
     }
     block_reduce_store<kScatterNV>(acc4, partials + blockIdx.x * kScatterNV);
 }
@@ -227,14 +255,16 @@ __global__ __launch_bounds__(kBlock) void k_scatter_fix(DevGraph g, int d, Scatt
     double acc4[kScatterNV] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t s = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; s < g.nspecial;
          s += int64_t(gridDim.x) * GPB) {
-        const int64_t v = g.special[s];
-        const int64_t vb = g.inc_ptr[v], ve = g.inc_ptr[v + 1];
-        double acc[NPER], dg[NPER];
+        const int4 sp = g.special[s];
+        const int64_t v = sp.x, vb = sp.y, ve = sp.z;
+        double acc[NPER], dg[NPER], xr[NPER], ar[NPER];
+        load_row<LPR, NPER>(so.X, v, d, gl, xr);
+        load_row<LPR, NPER>(so.A, v, d, gl, ar);
 #pragma unroll
         for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = 0.0;
         if (ve > vb) {
             for (int64_t c = vb / C; c <= (ve - 1) / C; ++c) {
-                const double* cr = g.carry + (c * 2 + (g.chunk_v[c] == v ? 0 : 1)) * CW;
+                const double* cr = g.carry + (c * 2 + (c * C >= vb ? 0 : 1)) * CW;
 #pragma unroll
                 for (int t = 0; t < NPER; ++t) {
                     const int k = gl + LPR * t;
@@ -245,119 +275,18 @@ __global__ __launch_bounds__(kBlock) void k_scatter_fix(DevGraph g, int d, Scatt
                 }
             }
         }
-        scatter_finish<LPR, NPER, DIAG>(v, d, gl, so, acc, dg, acc4);
+        scatter_finish<LPR, NPER, DIAG>(v, d, gl, so, xr, ar, acc, dg, acc4);
     }
     block_reduce_store<kScatterNV>(acc4, partials + blockIdx.x * kScatterNV);
 }
 
 // ---- Newton matvec ------------------------------------------------------------
 
-template <int LPR, int NPER, int Q, int MODE>
-__device__ __forceinline__ void matvec_range(int64_t pa, int64_t pb, int d, int gl, int W,
-                                             const Inc* __restrict__ inc,
-                                             const double* __restrict__ V,
-                                             const double* __restrict__ Pi, const Payload& pl,
-                                             const double* __restrict__ w, double gamma,
-                                             const double (&vi)[NPER], double (&acc)[NPER]) {
-    constexpr int U = Unroll<NPER>::U;
-    constexpr bool PAY = MODE == 0 || MODE == 2;
-    constexpr int QP = MODE == 2 ? kQ2 : Q;
-    for (int64_t p0 = pa; p0 < pb; p0 += U) {
-        Meta mt[U];
-        double vo[U][NPER];
-        double pv[U][NPER];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (p0 + u < pb) mt[u] = load_meta<QP, PAY, MODE == 2>(inc, p0 + u, pl, w, gamma);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool ok = p0 + u < pb;
-            const bool rows = ok && PAY && QP == kQ2 && mt[u].f != 0.0;
-#pragma unroll
-            for (int t = 0; t < NPER; ++t) {
-                const int k = gl + LPR * t;
-                vo[u][t] = (ok && k < d) ? V[mt[u].o * d + k] : 0.0;
-                pv[u][t] = (rows && k < d) ? Pi[mt[u].l * d + k] : 0.0;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (p0 + u >= pb) break;
-            const Meta& m = mt[u];
-            double dl[NPER];
-#pragma unroll
-            for (int t = 0; t < NPER; ++t) dl[t] = vi[t] - vo[u][t];
-            if constexpr (MODE == 1) {
-#pragma unroll
-                for (int t = 0; t < NPER; ++t) acc[t] += dl[t];
-            } else if constexpr (MODE == 2) {
-                // adjoint curvature a (I - yhat yhat^T) on every edge with a > 0
-                if (m.a > 0.0) {
-                    double c = 0.0;
-#pragma unroll
-                    for (int t = 0; t < NPER; ++t) c += pv[u][t] * dl[t];
-                    c = group_sum<LPR>(c) * m.f;
-#pragma unroll
-                    for (int t = 0; t < NPER; ++t) acc[t] += m.a * dl[t] - c * pv[u][t];
-                }
-            } else if constexpr (Q == kQ2) {
-                // P = I inside the ball; a (I - yhat yhat^T) outside with
-                // yhat = Pi_l / r, applied as a dl - (a / r^2) <Pi_l, dl> Pi_l
-                if (m.a >= 1.0) {
-#pragma unroll
-                    for (int t = 0; t < NPER; ++t) acc[t] += dl[t];
-                } else if (m.a > 0.0) {
-                    double c = 0.0;
-#pragma unroll
-                    for (int t = 0; t < NPER; ++t) c += pv[u][t] * dl[t];
-                    c = group_sum<LPR>(c) * m.f;
-#pragma unroll
-                    for (int t = 0; t < NPER; ++t) acc[t] += m.a * dl[t] - c * pv[u][t];
-                }
-            } else if constexpr (Q == kQ1) {
-                // P = diag(1[|y_k| <= r])
-#pragma unroll
-                for (int t = 0; t < NPER; ++t)
-                    if (t < W && mask_bit<LPR>(pl.bits, m.l, W, 1, t, 0, gl)) acc[t] += dl[t];
-            } else {
-                // P = I inside; diag(1_S) - s_S s_S^T / |S| outside
-                if (m.cnt < 0) {
-#pragma unroll
-                    for (int t = 0; t < NPER; ++t) acc[t] += dl[t];
-                } else if (m.cnt > 0) {
-                    bool inS[NPER], neg[NPER];
-                    double sd = 0.0;
-#pragma unroll
-                    for (int t = 0; t < NPER; ++t) {
-                        inS[t] = (t < W) && mask_bit<LPR>(pl.bits, m.l, W, 2, t, 0, gl);
-                        neg[t] = (t < W) && mask_bit<LPR>(pl.bits, m.l, W, 2, t, 1, gl);
-                        if (inS[t]) sd += neg[t] ? -dl[t] : dl[t];
-                    }
-                    sd = group_sum<LPR>(sd) / double(m.cnt);
-#pragma unroll
-                    for (int t = 0; t < NPER; ++t)
-                        if (inS[t]) acc[t] += dl[t] - (neg[t] ? -sd : sd);
-                }
-            }
-        }
-    }
-}
-
 struct MatvecOut {
     double sigma, c0;
     const double* dscale;
     double* out;
 };
-
-template <int LPR, int NPER>
-__device__ __forceinline__ void load_row(const double* __restrict__ V, int64_t v, int d, int gl,
-                                         double (&r)[NPER]) {
-#pragma unroll
-    for (int t = 0; t < NPER; ++t) {
-        const int k = gl + LPR * t;
-        r[t] = (k < d) ? V[v * d + k] : 0.0;
-    }
-}
 
 template <int LPR, int NPER>
 __device__ __forceinline__ void matvec_finish(int64_t v, int d, int gl, const MatvecOut& mo,
@@ -375,48 +304,97 @@ __device__ __forceinline__ void matvec_finish(int64_t v, int d, int gl, const Ma
     }
 }
 
+// the flag and the residual partials are read in the same round of loads
 __device__ __forceinline__ bool cg_skip(const CgSkip& skip) {
-    if (skip.done && *skip.done) return true;
+    const int dn = skip.done ? *skip.done : 0;
     if (skip.rr_partials) {
         const double rr = block_sum_partials(skip.rr_partials, skip.nparts, 2, 1);
         if (rr <= skip.thr) return true;
     }
-    return false;
+    return dn != 0;
+}
+
+// acc += P_l dl for one incidence (dl = v_i - v_other)
+template <int LPR, int NPER, int Q, int MODE>
+__device__ __forceinline__ void matvec_term(const Meta& m, const double (&dl)[NPER],
+                                            const double (&pv)[NPER], uint32_t lb,
+                                            double (&acc)[NPER]) {
+    if constexpr (MODE == 1) {
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) acc[t] += dl[t];
+    } else if constexpr (MODE == 2) {
+        // adjoint curvature a (I - yhat yhat^T) on every edge with a > 0
+        if (m.a > 0.0) {
+            double c = 0.0;
+#pragma unroll
+            for (int t = 0; t < NPER; ++t) c += pv[t] * dl[t];
+            c = group_sum<LPR>(c) * m.f;
+#pragma unroll
+            for (int t = 0; t < NPER; ++t) acc[t] += m.a * dl[t] - c * pv[t];
+        }
+    } else if constexpr (Q == kQ2) {
+        // P = I inside the ball; a (I - yhat yhat^T) outside with
+        // yhat = Pi_l / r, applied as a dl - (a / r^2) <Pi_l, dl> Pi_l
+        if (m.a >= 1.0) {
+#pragma unroll
+            for (int t = 0; t < NPER; ++t) acc[t] += dl[t];
+        } else if (m.a > 0.0) {
+            double c = 0.0;
+#pragma unroll
+            for (int t = 0; t < NPER; ++t) c += pv[t] * dl[t];
+            c = group_sum<LPR>(c) * m.f;
+#pragma unroll
+            for (int t = 0; t < NPER; ++t) acc[t] += m.a * dl[t] - c * pv[t];
+        }
+    } else if constexpr (Q == kQ1) {
+        // P = diag(1[|y_k| <= r])
+#pragma unroll
+        for (int t = 0; t < NPER; ++t)
+            if ((lb >> t) & 1u) acc[t] += dl[t];
+    } else {
+        // P = I inside; diag(1_S) - s_S s_S^T / |S| outside
+        if (m.cnt < 0) {
+#pragma unroll
+            for (int t = 0; t < NPER; ++t) acc[t] += dl[t];
+        } else if (m.cnt > 0) {
+            double sd = 0.0;
+#pragma unroll
+            for (int t = 0; t < NPER; ++t)
+                if ((lb >> t) & 1u) sd += ((lb >> (16 + t)) & 1u) ? -dl[t] : dl[t];
+            sd = group_sum<LPR>(sd) / double(m.cnt);
+#pragma unroll
+            for (int t = 0; t < NPER; ++t)
+                if ((lb >> t) & 1u) acc[t] += dl[t] - (((lb >> (16 + t)) & 1u) ? -sd : sd);
+        }
+    }
 }
 
 template <int LPR, int NPER, int Q, int MODE>
 __global__ __launch_bounds__(kBlock) void k_matvec_chunk(DevGraph g, int d,
                                                          const double* __restrict__ V,
                                                          const double* __restrict__ Pi,
-                                                         Payload pl, double gamma, MatvecOut mo,
+                                                         Payload pl, MatvecOut mo,
                                                          double* __restrict__ partials,
                                                          CgSkip skip) {
     if (cg_skip(skip)) return;
+    constexpr int U = Unroll<NPER>::U;
+    constexpr bool PAY = MODE != 1;
+    constexpr int QP = MODE == 2 ? kQ2 : Q;
     const int gl = (threadIdx.x & 63) % LPR;
     constexpr int GPB = kBlock / LPR;
-    const int W = (d + LPR - 1) / LPR;
-    const int64_t T = g.nent;
-    const int C = g.chunk;
     const int CW = 2 * d;
-    double dot[1] = {0.0};
+    double dot = 0.0;
     for (int64_t c = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; c < g.nchunks;
          c += int64_t(gridDim.x) * GPB) {
-        const int64_t cs = c * C;
-        const int64_t ce = cs + C < T ? cs + C : T;
-        int64_t v = g.chunk_v[c];
-        int64_t p = cs;
+        const ChunkCtx cx = chunk_ctx(g, c);
+        int64_t vcur = -1;
         bool first = true;
-        while (p < ce) {
-            const int64_t vb = g.inc_ptr[v], ve = g.inc_ptr[v + 1];
-            const int64_t se = ve < ce ? ve : ce;
-            double vi[NPER], acc[NPER];
-            load_row<LPR, NPER>(V, v, d, gl, vi);
+        double vi[NPER], acc[NPER];
 #pragma unroll
-            for (int t = 0; t < NPER; ++t) acc[t] = 0.0;
-            matvec_range<LPR, NPER, Q, MODE>(p, se, d, gl, W, g.inc, V, Pi, pl, g.w, gamma, vi,
-                                             acc);
-            if (vb >= cs && ve <= ce) {
-                matvec_finish<LPR, NPER>(v, d, gl, mo, vi, acc, dot[0]);
+        for (int t = 0; t < NPER; ++t) vi[t] = acc[t] = 0.0;
+        auto flush = [&](bool cut) {
+            if (!cut) {
+                matvec_finish<LPR, NPER>(vcur, d, gl, mo, vi, acc, dot);
             } else {
                 double* cr = g.carry + (c * 2 + (first ? 0 : 1)) * CW;
 #pragma unroll
@@ -425,15 +403,77 @@ __global__ __launch_bounds__(kBlock) void k_matvec_chunk(DevGraph g, int d,
                     if (k < d) cr[k] = acc[t];
                 }
             }
-            p = se;
-            first = false;
-            if (p < ce) {
-                ++v;
-                while (g.inc_ptr[v + 1] <= p) ++v;  // skip isolated vertices
+        };
+        for (int64_t p0 = cx.cs; p0 < cx.ce; p0 += U) {
+            Meta mt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (p0 + u < cx.ce) mt[u] = load_meta<QP, PAY, MODE == 2>(g, p0 + u, pl);
+            // the first vertex starting in this batch has its row gathered
+            // with the batch; any further one is loaded when reached
+            int un = -1;
+            int64_t vnew = -1;
+            double vn[NPER];
+            if constexpr (Unroll<NPER>::PREFETCH) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (un < 0 && p0 + u < cx.ce &&
+                        mt[u].v != (u == 0 ? vcur : int64_t(mt[u > 0 ? u - 1 : 0].v))) {
+                        un = u;
+                        vnew = mt[u].v;
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < NPER; ++t) {
+                    const int k = gl + LPR * t;
+                    vn[t] = (vnew >= 0 && k < d) ? V[vnew * d + k] : 0.0;
+                }
+            }
+            double vo[U][NPER], pv[U][NPER];
+            uint32_t lb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = p0 + u < cx.ce;
+                const bool rows = ok && PAY && QP == kQ2 && mt[u].f != 0.0;
+#pragma unroll
+                for (int t = 0; t < NPER; ++t) {
+                    const int k = gl + LPR * t;
+                    vo[u][t] = (ok && k < d) ? V[int64_t(mt[u].o) * d + k] : 0.0;
+                    pv[u][t] = (rows && k < d) ? Pi[int64_t(mt[u].l) * d + k] : 0.0;
+                }
+                lb[u] = 0u;
+                if constexpr (PAY && QP != kQ2)
+                    if (ok) lb[u] = pl.lbits[int64_t(mt[u].l) * LPR + gl];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (p0 + u >= cx.ce) break;
+                const Meta& m = mt[u];
+                if (m.v != vcur) {
+                    if (vcur >= 0) {
+                        flush(first && vcur == cx.vprev);
+                        first = false;
+                    }
+                    vcur = m.v;
+                    if (u == un) {
+#pragma unroll
+                        for (int t = 0; t < NPER; ++t) vi[t] = vn[t];
+                    } else {
+                        load_row<LPR, NPER>(V, vcur, d, gl, vi);
+                    }
+#pragma unroll
+                    for (int t = 0; t < NPER; ++t) acc[t] = 0.0;
+                }
+                double dl[NPER];
+#pragma unroll
+                for (int t = 0; t < NPER; ++t) dl[t] = vi[t] - vo[u][t];
+                matvec_term<LPR, NPER, Q, MODE>(m, dl, pv[u], lb[u], acc);
             }
         }
+        if (vcur >= 0) flush((first && vcur == cx.vprev) || vcur == cx.vnext);
     }
-    block_reduce_store<kMatvecNV>(dot, partials + blockIdx.x * kMatvecNV);
+    double dt[1] = {dot};
+    block_reduce_store<kMatvecNV>(dt, partials + blockIdx.x * kMatvecNV);
 }
 
 template <int LPR, int NPER>
@@ -446,18 +486,18 @@ __global__ __launch_bounds__(kBlock) void k_matvec_fix(DevGraph g, int d,
     constexpr int GPB = kBlock / LPR;
     const int C = g.chunk;
     const int CW = 2 * d;
-    double dot[1] = {0.0};
+    double dot = 0.0;
     for (int64_t s = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; s < g.nspecial;
          s += int64_t(gridDim.x) * GPB) {
-        const int64_t v = g.special[s];
-        const int64_t vb = g.inc_ptr[v], ve = g.inc_ptr[v + 1];
+        const int4 sp = g.special[s];
+        const int64_t v = sp.x, vb = sp.y, ve = sp.z;
         double vi[NPER], acc[NPER];
         load_row<LPR, NPER>(V, v, d, gl, vi);
 #pragma unroll
         for (int t = 0; t < NPER; ++t) acc[t] = 0.0;
         if (ve > vb) {
             for (int64_t c = vb / C; c <= (ve - 1) / C; ++c) {
-                const double* cr = g.carry + (c * 2 + (g.chunk_v[c] == v ? 0 : 1)) * CW;
+                const double* cr = g.carry + (c * 2 + (c * C >= vb ? 0 : 1)) * CW;
 #pragma unroll
                 for (int t = 0; t < NPER; ++t) {
                     const int k = gl + LPR * t;
@@ -465,9 +505,10 @@ __global__ __launch_bounds__(kBlock) void k_matvec_fix(DevGraph g, int d,
                 }
             }
         }
-        matvec_finish<LPR, NPER>(v, d, gl, mo, vi, acc, dot[0]);
+        matvec_finish<LPR, NPER>(v, d, gl, mo, vi, acc, dot);
     }
-    block_reduce_store<kMatvecNV>(dot, partials + blockIdx.x * kMatvecNV);
+    double dt[1] = {dot};
+    block_reduce_store<kMatvecNV>(dt, partials + blockIdx.x * kMatvecNV);
 }
 
 }  // namespace
@@ -476,6 +517,7 @@ int launch_scatter(const DevGraph& g, int d, int qk, double cx, const double* X,
                    const double* A, double cz, const double* Z, double* out, bool diag, Payload pl,
                    double gamma, double sigma, double* Dinv, double* partials, hipStream_t s,
                    double* rowstats) {
+    (void)gamma;  // the Jacobian payload already holds 1 / (gamma w)
     int total = 0;
     ScatterOut so{cx, ca, cz, sigma, X, A, out, Dinv, rowstats};
     dispatch_row(d, [&](auto L, auto N) {
@@ -485,7 +527,7 @@ int launch_scatter(const DevGraph& g, int d, int qk, double cx, const double* X,
         if (!diag) {
             if (g1 > 0)
                 hipLaunchKernelGGL((k_scatter_chunk<lpr, nper, kQ2, false>), dim3(g1), dim3(kBlock),
-                                   0, s, g, d, so, Z, pl, gamma, partials);
+                                   0, s, g, d, so, Z, pl, partials);
             hipLaunchKernelGGL((k_scatter_fix<lpr, nper, false>), dim3(g2), dim3(kBlock), 0, s, g,
                                d, so, partials + g1 * kScatterNV);
         } else {
@@ -493,7 +535,7 @@ int launch_scatter(const DevGraph& g, int d, int qk, double cx, const double* X,
                 dispatch_q(qk, [&](auto Qc) {
                     constexpr int q = decltype(Qc)::value;
                     hipLaunchKernelGGL((k_scatter_chunk<lpr, nper, q, true>), dim3(g1),
-                                       dim3(kBlock), 0, s, g, d, so, Z, pl, gamma, partials);
+                                       dim3(kBlock), 0, s, g, d, so, Z, pl, partials);
                 });
             }
             hipLaunchKernelGGL((k_scatter_fix<lpr, nper, true>), dim3(g2), dim3(kBlock), 0, s, g,
@@ -507,6 +549,7 @@ int launch_scatter(const DevGraph& g, int d, int qk, double cx, const double* X,
 int launch_matvec(const DevGraph& g, int d, int qk, int mode, const double* V, const double* Pi,
                   Payload pl, double gamma, double sigma, double c0, const double* dscale,
                   double* out, double* partials, CgSkip skip, hipStream_t s) {
+    (void)gamma;  // the Jacobian payload already holds 1 / (gamma w)
     int total = 0;
     MatvecOut mo{sigma, c0, dscale, out};
     dispatch_row(d, [&](auto L, auto N) {
@@ -516,15 +559,15 @@ int launch_matvec(const DevGraph& g, int d, int qk, int mode, const double* V, c
         if (g1 > 0) {
             if (mode == 1) {
                 hipLaunchKernelGGL((k_matvec_chunk<lpr, nper, kQ2, 1>), dim3(g1), dim3(kBlock), 0,
-                                   s, g, d, V, Pi, pl, gamma, mo, partials, skip);
+                                   s, g, d, V, Pi, pl, mo, partials, skip);
             } else if (mode == 2) {
                 hipLaunchKernelGGL((k_matvec_chunk<lpr, nper, kQ2, 2>), dim3(g1), dim3(kBlock), 0,
-                                   s, g, d, V, Pi, pl, gamma, mo, partials, skip);
+                                   s, g, d, V, Pi, pl, mo, partials, skip);
             } else {
                 dispatch_q(qk, [&](auto Qc) {
                     constexpr int q = decltype(Qc)::value;
                     hipLaunchKernelGGL((k_matvec_chunk<lpr, nper, q, 0>), dim3(g1), dim3(kBlock),
-                                       0, s, g, d, V, Pi, pl, gamma, mo, partials, skip);
+                                       0, s, g, d, V, Pi, pl, mo, partials, skip);
                 });
             }
         }

@@ -64,8 +64,8 @@ ccm_status path_vjp(const double* A, int64_t n, int d, const int* src, const int
         st = membership_build(labels, n, K, d, s, cg, err);
         if (st != CCM_OK) return st;
         const int64_t NK = K * d, NV = n * d;
-        DevMem alpha, Pi, rhs, x, r, z, p, q, pv, ov, minv, part, sc;
-        HIPCHK(alpha.alloc(size_t(std::max<int64_t>(m, 1)) * 8, s));
+        DevMem ipay, Pi, rhs, x, r, z, p, q, pv, ov, minv, part, sc;
+        HIPCHK(ipay.alloc(size_t(std::max<int64_t>(og.g.nent, 1)) * 16, s));
         HIPCHK(Pi.alloc(size_t(std::max<int64_t>(m, 1)) * d * 8, s));
         for (DevMem* b : {&rhs, &x, &r, &z, &p, &q}) HIPCHK(b->alloc(size_t(NK) * 8, s));
         HIPCHK(pv.alloc(size_t(NV) * 8, s));
@@ -87,8 +87,8 @@ ccm_status path_vjp(const double* A, int64_t n, int d, const int* src, const int
             out = hs[0];
             return CCM_OK;
         };
-        Payload pl{alpha.as<double>(), nullptr, nullptr};
-        launch_adj_payload(og.g, d, X, labels, gamma, alpha.as<double>(), Pi.as<double>(), s);
+        Payload pl{ipay.as<double2>(), nullptr};
+        launch_adj_payload(og.g, d, X, labels, gamma, ipay.as<double2>(), Pi.as<double>(), s);
         launch_inv_sizes(K, cg.g.inc_ptr, minv.as<double>(), s);
         // g_c = sum over members of dL/dx
         launch_scatter(cg.g, d, kQ2, 0.0, nullptr, 0.0, nullptr, 1.0, dLdX, rhs.as<double>(),

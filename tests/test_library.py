@@ -30,3 +30,11 @@ def test_struct_sizes():
     o = ccm.ccm_default_options()
     assert o.method == 0 and o.max_outer == 300 and o.cg_max_iter == 500
     assert ccm.ccm_version().startswith("libccm")
+
+
+def test_binding_wraps_every_compute_entry_point():
+    import paper_2501_15964_amd as pkg
+    helpers = {"ccm_status_string", "ccm_last_error"}
+    for name in pkg.EXPORTED_SYMBOLS:
+        if name not in helpers:
+            assert name in pkg.__all__ and callable(getattr(pkg, name)), name
