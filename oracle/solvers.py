@@ -339,7 +339,8 @@ def solve_path(A, src, dst, w, gammas, q, tol=1e-6, method="ssnal", opts=None):
     for g in gammas:
         t0 = time.perf_counter()
         if method == "ssnal":
-            X, U, sig, info = ssnal(A, src, dst, w, g, q, tol, X0=X, U0=U, sigma=sig, opts=opts)
+            # the penalty restarts at sigma0 for every gamma (X and U are warm)
+            X, U, _, info = ssnal(A, src, dst, w, g, q, tol, X0=X, U0=U, sigma=None, opts=opts)
         elif method == "admm":
             X, U, (Z, L, sig), info = admm(A, src, dst, w, g, q, tol, X0=X, Z0=Z, L0=L,
                                            sigma=sig, opts=opts)

@@ -64,19 +64,26 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* out)
 
 // Deterministic sums of K partials arrays (array i: count[i] entries with
 // stride nv[i], starting at ptr[i]), computed identically by every block
-// that calls it: thread t adds entries t, t + blockDim, ... in order, then a
+// that calls it: thread t adds entries t, t + 64 WAVES, ... in order, then a
 // fixed xor butterfly inside the wave and the waves in order.  All K sums
-// share one pass of loads and one pair of barriers.  Uses the whole block;
-// the results are returned to every thread.
-template <int K>
+// share one pass of loads and one pair of barriers.  The block must have
+// exactly WAVES waves; the results are returned to every thread.
+template <int K, int WAVES = kWaves>
 __device__ __forceinline__ void block_sums(const double* const (&ptr)[K], const int (&count)[K],
                                            const int (&nv)[K], double (&out)[K]) {
-    __shared__ double red[kWaves][K];
+    __shared__ double red[WAVES][K];
     double x[K];
+    int maxc = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         x[i] = 0.0;
-        for (int p = threadIdx.x; p < count[i]; p += blockDim.x) x[i] += ptr[i][p * nv[i]];
+        maxc = count[i] > maxc ? count[i] : maxc;
+    }
+    // the K arrays are read in the same loop so their loads overlap
+    for (int p = threadIdx.x; p < maxc; p += WAVES * 64) {
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (p < count[i]) x[i] += ptr[i][p * nv[i]];
     }
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -95,7 +102,7 @@ __device__ __forceinline__ void block_sums(const double* const (&ptr)[K], const 
     for (int i = 0; i < K; ++i) {
         double t = 0.0;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) t += red[w][i];
+        for (int w = 0; w < WAVES; ++w) t += red[w][i];
         out[i] = t;
     }
 }

@@ -871,6 +871,9 @@ ccm_status Solver::run_path(const double* gammas, int T, const double* Xw, const
             I.admm_state = false;
             // f_p = f_d = 0 and every residual is 0
         } else if (I.o.method == CCM_SSNAL) {
+            // the penalty restarts at sigma0 for every gamma: a penalty grown
+            // on one problem makes the next, more fused one ill-conditioned
+            I.sigma = I.o.sigma0;
             CHK(I.ssnal(gamma, stat, st, res));
         } else if (I.o.method == CCM_ADMM) {
             CHK(I.admm(gamma, stat, st, res));
@@ -950,6 +953,7 @@ ccm_status Solver::run_batched(const double* gammas, int T, const BatchSpec& b) 
             launch_fill(I.U, I.M, 0.0, I.s);
             I.inst_res.assign(S, {0, 0, 0, 0, 0, 0, 0});
         } else {
+            I.sigma = I.o.sigma0;
             CHK(I.ssnal(gamma, stat, st, res));
         }
         int ncl = 0;

@@ -122,9 +122,13 @@ __global__ __launch_bounds__(kBlock) void k_trial(int64_t N, const double* __res
     block_reduce_store<kAxpyNV>(acc, partials + blockIdx.x * kAxpyNV);
 }
 
+// one wide block: the partials of up to a few thousand blocks are read in
+// four loads per thread
+constexpr int kFinalizeWaves = 16;
+
 template <int NV>
-__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials,
-                                                     int nparts, double* __restrict__ out) {
+__global__ __launch_bounds__(kFinalizeWaves * 64) void k_finalize(const double* __restrict__ partials,
+                                                                  int nparts, double* __restrict__ out) {
     const double* ptr[NV];
     int cnt[NV], st[NV];
 #pragma unroll
@@ -134,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
         st[c] = NV;
     }
     double t[NV];
-    block_sums<NV>(ptr, cnt, st, t);
+    block_sums<NV, kFinalizeWaves>(ptr, cnt, st, t);
     if (threadIdx.x < NV) {
 #pragma unroll
         for (int c = 0; c < NV; ++c)
@@ -384,13 +388,13 @@ int launch_trial(int64_t N, const double* X, const double* D, double alpha, cons
 
 void launch_finalize(const double* partials, int nparts, int nv, double* out, hipStream_t s) {
     switch (nv) {
-        case 1: hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kBlock), 0, s, partials, nparts, out); break;
-        case 2: hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kBlock), 0, s, partials, nparts, out); break;
-        case 3: hipLaunchKernelGGL(k_finalize<3>, dim3(1), dim3(kBlock), 0, s, partials, nparts, out); break;
-        case 4: hipLaunchKernelGGL(k_finalize<4>, dim3(1), dim3(kBlock), 0, s, partials, nparts, out); break;
-        case 5: hipLaunchKernelGGL(k_finalize<5>, dim3(1), dim3(kBlock), 0, s, partials, nparts, out); break;
-        case 6: hipLaunchKernelGGL(k_finalize<6>, dim3(1), dim3(kBlock), 0, s, partials, nparts, out); break;
-        default: hipLaunchKernelGGL(k_finalize<7>, dim3(1), dim3(kBlock), 0, s, partials, nparts, out); break;
+        case 1: hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kFinalizeWaves * 64), 0, s, partials, nparts, out); break;
+        case 2: hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kFinalizeWaves * 64), 0, s, partials, nparts, out); break;
+        case 3: hipLaunchKernelGGL(k_finalize<3>, dim3(1), dim3(kFinalizeWaves * 64), 0, s, partials, nparts, out); break;
+        case 4: hipLaunchKernelGGL(k_finalize<4>, dim3(1), dim3(kFinalizeWaves * 64), 0, s, partials, nparts, out); break;
+        case 5: hipLaunchKernelGGL(k_finalize<5>, dim3(1), dim3(kFinalizeWaves * 64), 0, s, partials, nparts, out); break;
+        case 6: hipLaunchKernelGGL(k_finalize<6>, dim3(1), dim3(kFinalizeWaves * 64), 0, s, partials, nparts, out); break;
+        default: hipLaunchKernelGGL(k_finalize<7>, dim3(1), dim3(kFinalizeWaves * 64), 0, s, partials, nparts, out); break;
     }
 }
 

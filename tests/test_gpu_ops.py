@@ -14,7 +14,18 @@ DIMS = [1, 2, 3, 5, 8, 31, 64, 65, 130, 784]
 
 
 def _graph(n, m, seed):
-    src, dst, w = synthdata.random_graph(n, m, seed)
+    """Random graph plus a hub (vertex 1 joined to every 2nd vertex, degree far
+    above any vertex-window width) and isolated vertices (the last three)."""
+    src, dst, w = synthdata.random_graph(n - 3, m, seed)
+    rng = np.random.default_rng(seed + 1)
+    hub = [(1, j) for j in range(2, n - 3, 2)]
+    keys = {(int(a), int(b)): float(c) for a, b, c in zip(src, dst, w)}
+    for a, b in hub:
+        keys.setdefault((a, b), float(rng.uniform(0.1, 1.0)))
+    e = sorted(keys)
+    src = np.array([a for a, _ in e], np.int32)
+    dst = np.array([b for _, b in e], np.int32)
+    w = np.array([keys[k] for k in e])
     return src, dst, w
 
 
