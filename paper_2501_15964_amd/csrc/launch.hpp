@@ -32,6 +32,16 @@ inline void dispatch_row(int d, F&& f) {
     else f(IC<64>{}, IC<16>{});
 }
 
+// values per lane of a whole-wave row layout (64 lanes): ceil(d / 64) rounded up
+template <class F>
+inline void dispatch_fix(int d, F&& f) {
+    if (d <= 64) f(IC<1>{});
+    else if (d <= 128) f(IC<2>{});
+    else if (d <= 256) f(IC<4>{});
+    else if (d <= 512) f(IC<8>{});
+    else f(IC<16>{});
+}
+
 template <class F>
 inline void dispatch_q(int qk, F&& f) {
     if (qk == kQ1) f(IC<kQ1>{});

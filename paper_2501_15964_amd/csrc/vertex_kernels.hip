@@ -66,6 +66,84 @@ __device__ __forceinline__ Meta load_meta(const DevGraph& g, int64_t p, const Pa
     return m;
 }
 
+// Chunk width of each row layout (the host's chunk_for(d) for the d the
+// layout serves).
+template <int LPR, int NPER>
+constexpr int chunk_of() {
+    return LPR * NPER <= 64 ? 16 : LPR * NPER <= 256 ? 32 : 64;
+}
+
+// Incidence data of a whole chunk, loaded once at chunk start and spread over
+// the lanes of the row group (entry j LPR + lane in slot j); an entry's data
+// is then fetched with lane shuffles instead of another round of loads.
+template <int LPR, int NM>
+struct ChunkMeta {
+    int e[NM], o[NM], v[NM];
+    double a[NM], ir[NM];
+};
+
+template <int LPR, int NM, int Q, bool PAY>
+__device__ __forceinline__ void chunk_meta_load(const DevGraph& g, int64_t cs, int64_t ce, int gl,
+                                                const Payload& pl, ChunkMeta<LPR, NM>& cm) {
+#pragma unroll
+    for (int j = 0; j < NM; ++j) {
+        const int64_t p = cs + j * LPR + gl;
+        cm.e[j] = 0;
+        cm.o[j] = 0;
+        cm.v[j] = -1;
+        cm.a[j] = 1.0;
+        cm.ir[j] = 0.0;
+        if (p < ce) {
+            const Inc in = g.inc[p];
+            cm.e[j] = in.e;
+            cm.o[j] = in.o;
+            cm.v[j] = g.irow[p];
+            if constexpr (PAY && Q == kQ2) {
+                const double2 q = pl.ipay[p];
+                cm.a[j] = q.x;
+                cm.ir[j] = q.y;
+            } else if constexpr (PAY && Q == kQInf) {
+                cm.a[j] = pl.ipay[p].x;
+            }
+        }
+    }
+}
+
+template <int LPR, int NM, int Q, bool PAY, bool ADJ>
+__device__ __forceinline__ Meta chunk_meta_get(const ChunkMeta<LPR, NM>& cm, int q) {
+    const int j = q / LPR, src = q % LPR;
+    int e = cm.e[0], o = cm.o[0], v = cm.v[0];
+    double a = cm.a[0], ir = cm.ir[0];
+#pragma unroll
+    for (int jj = 1; jj < NM; ++jj) {
+        if (j == jj) {
+            e = cm.e[jj];
+            o = cm.o[jj];
+            v = cm.v[jj];
+            a = cm.a[jj];
+            ir = cm.ir[jj];
+        }
+    }
+    Meta m;
+    e = __shfl(e, src, LPR);
+    m.o = __shfl(o, src, LPR);
+    m.v = __shfl(v, src, LPR);
+    m.pos = e >= 0;
+    m.l = m.pos ? e : ~e;
+    m.a = 1.0;
+    m.ir = 0.0;
+    m.f = 0.0;
+    m.cnt = -1;
+    if constexpr (PAY && Q == kQ2) {
+        m.a = __shfl(a, src, LPR);
+        m.ir = __shfl(ir, src, LPR);
+        if ((ADJ || m.a < 1.0) && m.a > 0.0) m.f = m.a * m.ir * m.ir;
+    } else if constexpr (PAY && Q == kQInf) {
+        m.cnt = int(__shfl(a, src, LPR));
+    }
+    return m;
+}
+
 struct ChunkCtx {
     int64_t cs, ce;      // incidence range of the chunk
     int64_t vprev;       // vertex of entry cs - 1 (-1 if none)
@@ -245,36 +323,71 @@ __global__ __launch_bounds__(kBlock) void k_scatter_chunk(DevGraph g, int d, Sca
     block_reduce_store<kScatterNV>(acc4, partials + blockIdx.x * kScatterNV);
 }
 
+// Sum, in chunk order, of the partial rows a cut vertex left in the carry
+// slots of chunks c0..c1 (slot 0 where the chunk starts inside the vertex's
+// range, else 1); the first three are loaded in one round.
 template <int LPR, int NPER, bool DIAG>
-__global__ __launch_bounds__(kBlock) void k_scatter_fix(DevGraph g, int d, ScatterOut so,
-                                                        double* __restrict__ partials) {
-    const int gl = (threadIdx.x & 63) % LPR;
-    constexpr int GPB = kBlock / LPR;
+__device__ __forceinline__ void sum_carries(const DevGraph& g, int d, int gl, int64_t vb,
+                                            int64_t ve, double (&acc)[NPER],
+                                            double (&dg)[NPER]) {
+#pragma unroll
+    for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = 0.0;
+    if (ve <= vb) return;
     const int C = g.chunk;
     const int CW = 2 * d;
+    const int64_t c0 = vb / C, c1 = (ve - 1) / C;
+    double p[3][NPER], q[3][NPER];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int64_t c = c0 + j;
+        const double* cr = g.carry + (c * 2 + (c * C >= vb ? 0 : 1)) * CW;
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            const bool ok = c <= c1 && k < d;
+            p[j][t] = ok ? cr[k] : 0.0;
+            q[j][t] = (DIAG && ok) ? cr[d + k] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        if (c0 + j > c1) break;
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            acc[t] += p[j][t];
+            if constexpr (DIAG) dg[t] += q[j][t];
+        }
+    }
+    for (int64_t c = c0 + 3; c <= c1; ++c) {
+        const double* cr = g.carry + (c * 2 + (c * C >= vb ? 0 : 1)) * CW;
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            if (k < d) {
+                acc[t] += cr[k];
+                if constexpr (DIAG) dg[t] += cr[d + k];
+            }
+        }
+    }
+}
+
+// The fix-up kernels use a whole wave per vertex row (NPER = ceil(d / 64)):
+// they are latency-bound, and more waves in flight hide more of it.
+template <int NPER, bool DIAG>
+__global__ __launch_bounds__(kBlock) void k_scatter_fix(DevGraph g, int d, ScatterOut so,
+                                                        double* __restrict__ partials) {
+    constexpr int LPR = 64;
+    const int gl = threadIdx.x & 63;
+    constexpr int GPB = kBlock / LPR;
     double acc4[kScatterNV] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t s = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; s < g.nspecial;
          s += int64_t(gridDim.x) * GPB) {
         const int4 sp = g.special[s];
-        const int64_t v = sp.x, vb = sp.y, ve = sp.z;
+        const int64_t v = sp.x;
         double acc[NPER], dg[NPER], xr[NPER], ar[NPER];
         load_row<LPR, NPER>(so.X, v, d, gl, xr);
         load_row<LPR, NPER>(so.A, v, d, gl, ar);
-#pragma unroll
-        for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = 0.0;
-        if (ve > vb) {
-            for (int64_t c = vb / C; c <= (ve - 1) / C; ++c) {
-                const double* cr = g.carry + (c * 2 + (c * C >= vb ? 0 : 1)) * CW;
-#pragma unroll
-                for (int t = 0; t < NPER; ++t) {
-                    const int k = gl + LPR * t;
-                    if (k < d) {
-                        acc[t] += cr[k];
-                        if constexpr (DIAG) dg[t] += cr[d + k];
-                    }
-                }
-            }
-        }
+        sum_carries<LPR, NPER, DIAG>(g, d, gl, sp.y, sp.z, acc, dg);
         scatter_finish<LPR, NPER, DIAG>(v, d, gl, so, xr, ar, acc, dg, acc4);
     }
     block_reduce_store<kScatterNV>(acc4, partials + blockIdx.x * kScatterNV);
@@ -380,6 +493,8 @@ __global__ __launch_bounds__(kBlock) void k_matvec_chunk(DevGraph g, int d,
     constexpr int U = Unroll<NPER>::U;
     constexpr bool PAY = MODE != 1;
     constexpr int QP = MODE == 2 ? kQ2 : Q;
+    constexpr int NM = chunk_of<LPR, NPER>() / LPR > 0 ? chunk_of<LPR, NPER>() / LPR : 1;
+    constexpr bool PF = NM <= 4;  // chunk data fits a few registers per lane
     const int gl = (threadIdx.x & 63) % LPR;
     constexpr int GPB = kBlock / LPR;
     const int CW = 2 * d;
@@ -387,6 +502,8 @@ __global__ __launch_bounds__(kBlock) void k_matvec_chunk(DevGraph g, int d,
     for (int64_t c = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; c < g.nchunks;
          c += int64_t(gridDim.x) * GPB) {
         const ChunkCtx cx = chunk_ctx(g, c);
+        ChunkMeta<LPR, PF ? NM : 1> cm;
+        if constexpr (PF) chunk_meta_load<LPR, NM, QP, PAY>(g, cx.cs, cx.ce, gl, pl, cm);
         int64_t vcur = -1;
         bool first = true;
         double vi[NPER], acc[NPER];
@@ -408,7 +525,12 @@ __global__ __launch_bounds__(kBlock) void k_matvec_chunk(DevGraph g, int d,
             Meta mt[U];
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (p0 + u < cx.ce) mt[u] = load_meta<QP, PAY, MODE == 2>(g, p0 + u, pl);
+                if (p0 + u < cx.ce) {
+                    if constexpr (PF)
+                        mt[u] = chunk_meta_get<LPR, NM, QP, PAY, MODE == 2>(cm, int(p0 + u - cx.cs));
+                    else
+                        mt[u] = load_meta<QP, PAY, MODE == 2>(g, p0 + u, pl);
+                }
             // the first vertex starting in this batch has its row gathered
             // with the batch; any further one is loaded when reached
             int un = -1;
@@ -476,35 +598,23 @@ __global__ __launch_bounds__(kBlock) void k_matvec_chunk(DevGraph g, int d,
     block_reduce_store<kMatvecNV>(dt, partials + blockIdx.x * kMatvecNV);
 }
 
-template <int LPR, int NPER>
+template <int NPER>
 __global__ __launch_bounds__(kBlock) void k_matvec_fix(DevGraph g, int d,
                                                        const double* __restrict__ V, MatvecOut mo,
                                                        double* __restrict__ partials,
                                                        CgSkip skip) {
     if (cg_skip(skip)) return;
-    const int gl = (threadIdx.x & 63) % LPR;
+    constexpr int LPR = 64;
+    const int gl = threadIdx.x & 63;
     constexpr int GPB = kBlock / LPR;
-    const int C = g.chunk;
-    const int CW = 2 * d;
     double dot = 0.0;
     for (int64_t s = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; s < g.nspecial;
          s += int64_t(gridDim.x) * GPB) {
         const int4 sp = g.special[s];
-        const int64_t v = sp.x, vb = sp.y, ve = sp.z;
-        double vi[NPER], acc[NPER];
+        const int64_t v = sp.x;
+        double vi[NPER], acc[NPER], unused[NPER];
         load_row<LPR, NPER>(V, v, d, gl, vi);
-#pragma unroll
-        for (int t = 0; t < NPER; ++t) acc[t] = 0.0;
-        if (ve > vb) {
-            for (int64_t c = vb / C; c <= (ve - 1) / C; ++c) {
-                const double* cr = g.carry + (c * 2 + (c * C >= vb ? 0 : 1)) * CW;
-#pragma unroll
-                for (int t = 0; t < NPER; ++t) {
-                    const int k = gl + LPR * t;
-                    if (k < d) acc[t] += cr[k];
-                }
-            }
-        }
+        sum_carries<LPR, NPER, false>(g, d, gl, sp.y, sp.z, acc, unused);
         matvec_finish<LPR, NPER>(v, d, gl, mo, vi, acc, dot);
     }
     double dt[1] = {dot};
@@ -523,13 +633,16 @@ int launch_scatter(const DevGraph& g, int d, int qk, double cx, const double* X,
     dispatch_row(d, [&](auto L, auto N) {
         constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
         const int g1 = g.nchunks > 0 ? row_grid(g.nchunks, lpr) : 0;
-        const int g2 = row_grid(g.nspecial, lpr);
+        const int g2 = row_grid(g.nspecial, 64);
         if (!diag) {
             if (g1 > 0)
                 hipLaunchKernelGGL((k_scatter_chunk<lpr, nper, kQ2, false>), dim3(g1), dim3(kBlock),
                                    0, s, g, d, so, Z, pl, partials);
-            hipLaunchKernelGGL((k_scatter_fix<lpr, nper, false>), dim3(g2), dim3(kBlock), 0, s, g,
-                               d, so, partials + g1 * kScatterNV);
+            dispatch_fix(d, [&](auto F) {
+                constexpr int nf = decltype(F)::value;
+                hipLaunchKernelGGL((k_scatter_fix<nf, false>), dim3(g2), dim3(kBlock), 0, s, g, d,
+                                   so, partials + g1 * kScatterNV);
+            });
         } else {
             if (g1 > 0) {
                 dispatch_q(qk, [&](auto Qc) {
@@ -538,8 +651,11 @@ int launch_scatter(const DevGraph& g, int d, int qk, double cx, const double* X,
                                        dim3(kBlock), 0, s, g, d, so, Z, pl, partials);
                 });
             }
-            hipLaunchKernelGGL((k_scatter_fix<lpr, nper, true>), dim3(g2), dim3(kBlock), 0, s, g,
-                               d, so, partials + g1 * kScatterNV);
+            dispatch_fix(d, [&](auto F) {
+                constexpr int nf = decltype(F)::value;
+                hipLaunchKernelGGL((k_scatter_fix<nf, true>), dim3(g2), dim3(kBlock), 0, s, g, d,
+                                   so, partials + g1 * kScatterNV);
+            });
         }
         total = g1 + g2;
     });
@@ -555,7 +671,7 @@ int launch_matvec(const DevGraph& g, int d, int qk, int mode, const double* V, c
     dispatch_row(d, [&](auto L, auto N) {
         constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
         const int g1 = g.nchunks > 0 ? row_grid(g.nchunks, lpr) : 0;
-        const int g2 = row_grid(g.nspecial, lpr);
+        const int g2 = row_grid(g.nspecial, 64);
         if (g1 > 0) {
             if (mode == 1) {
                 hipLaunchKernelGGL((k_matvec_chunk<lpr, nper, kQ2, 1>), dim3(g1), dim3(kBlock), 0,
@@ -571,8 +687,11 @@ int launch_matvec(const DevGraph& g, int d, int qk, int mode, const double* V, c
                 });
             }
         }
-        hipLaunchKernelGGL((k_matvec_fix<lpr, nper>), dim3(g2), dim3(kBlock), 0, s, g, d, V, mo,
-                           partials + g1 * kMatvecNV, skip);
+        dispatch_fix(d, [&](auto F) {
+            constexpr int nf = decltype(F)::value;
+            hipLaunchKernelGGL((k_matvec_fix<nf>), dim3(g2), dim3(kBlock), 0, s, g, d, V, mo,
+                               partials + g1 * kMatvecNV, skip);
+        });
         total = g1 + g2;
     });
     return total;
