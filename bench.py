@@ -204,7 +204,8 @@ def main():
     ap.add_argument("--batched-budget", type=float, default=90.0,
                     help="wall-clock budget (s) of each (q, d) group of the batched leg")
     ap.add_argument("--no-profile", action="store_true",
-                    help="time without per-kernel HIP events (roofline then omitted)")
+                    help="time without HIP events around the matvec launches (roofline then "
+                         "omitted)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU: the path solver is "
@@ -222,13 +223,17 @@ def main():
     dev = torch.device("cuda:0")
     A = torch.from_numpy(A_np).to(dev)
     torch.cuda.synchronize()
-    opts = ccm.ccm_default_options(profile=0 if args.no_profile else 1)
+    # timed steps: HIP events around the Newton/CG matvec launches only (profile
+    # level 2), which the roofline figure needs; one extra untimed step with
+    # every kernel class timed (level 1) gives the per-class breakdown
+    opts = ccm.ccm_default_options(profile=0 if args.no_profile else 2)
+    opts_all = ccm.ccm_default_options(profile=1)
 
-    def step():
+    def step(o=opts):
         t0 = time.perf_counter()
         src, dst, w, phi = ccm.ccm_build_knn_graph(A, wl["k"], wl["phi"])
         t1 = time.perf_counter()
-        out = ccm.ccm_solve_path(A, src, dst, w, gammas, wl["q"], wl["tol"], opts=opts)
+        out = ccm.ccm_solve_path(A, src, dst, w, gammas, wl["q"], wl["tol"], opts=o)
         t2 = time.perf_counter()
         return out, (t1 - t0), (t2 - t1), int(src.numel()), phi
 
@@ -256,15 +261,18 @@ def main():
     if not args.no_profile:
         mv_ms = mv_bytes = 0.0
         mv_calls = 0
-        cls_ms = np.zeros(5)
-        cls_calls = np.zeros(5, dtype=np.int64)
         for r in results:
             for st in r[0]["stats"]:
                 mv_ms += st["kern_ms"][2]
                 mv_calls += st["kern_calls"][2]
                 mv_bytes += st["matvec_bytes"]
-                cls_ms += np.array(st["kern_ms"])
-                cls_calls += np.array(st["kern_calls"])
+        # per-class breakdown from one extra, untimed step with every class timed
+        extra = step(opts_all)
+        cls_ms = np.zeros(5)
+        cls_calls = np.zeros(5, dtype=np.int64)
+        for st in extra[0]["stats"]:
+            cls_ms += np.array(st["kern_ms"])
+            cls_calls += np.array(st["kern_calls"])
         if mv_ms > 0 and mv_calls > 0:
             avg_s = mv_ms / 1000.0 / mv_calls
             bytes_per_launch = mv_bytes / mv_calls
@@ -278,8 +286,9 @@ def main():
                         "launches": int(mv_calls),
                         "algorithmic_bytes_per_launch": round(bytes_per_launch)}
         names = ["edge", "scatter", "matvec", "cg_update", "other"]
-        kern = {names[c]: {"ms": round(float(cls_ms[c]) / args.steps, 3),
-                           "launches": int(cls_calls[c] // args.steps)} for c in range(5)}
+        kern = {names[c]: {"ms": round(float(cls_ms[c]), 3), "launches": int(cls_calls[c])}
+                for c in range(5)}
+        kern["note"] = "one untimed step with every kernel class timed (HIP events)"
 
     # achievable copy bandwidth of the same device (calibration, untimed)
     buf_a = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB

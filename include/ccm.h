@@ -76,7 +76,9 @@ typedef struct {
     int32_t max_iter;      /* ADMM / AMA iterations per gamma.  20000 */
     int32_t check_every;   /* ADMM / AMA: KKT test every this many iterations.  10 */
     int32_t cg_chunk;      /* CG iterations launched between host checks.  8 */
-    int32_t profile;       /* 1: time kernel classes with HIP events (ccm_stats.kern_*) */
+    int32_t profile;       /* 1: time every kernel class with HIP events (ccm_stats.kern_*);
+                              2: time only the Newton/CG matvec class (less host work);
+                              0: off */
     double sigma0;         /* initial penalty on a cold start; <= 0: method default
                               (10 for SSNAL, 1 for ADMM) */
     double sigma_max;      /* SSNAL penalty cap.  1e4 */
@@ -86,7 +88,7 @@ typedef struct {
 
 ccm_options ccm_default_options(void);
 
-/* Kernel classes timed when ccm_options.profile = 1. */
+/* Kernel classes timed when ccm_options.profile = 1 (only CCM_K_MATVEC when 2). */
 enum { CCM_K_EDGE = 0, CCM_K_SCATTER = 1, CCM_K_MATVEC = 2, CCM_K_CGUPDATE = 3,
        CCM_K_OTHER = 4, CCM_NK = 5 };
 
@@ -96,16 +98,20 @@ typedef struct {
     double seconds;                         /* wall time of this gamma (host clock) */
     double f_p, f_d;                        /* primal (CCM) value, dual value at Pi_C(U) */
     double sigma;                           /* penalty at exit */
-    double kern_ms[CCM_NK];                 /* profile = 1: summed kernel time per class */
-    int64_t kern_calls[CCM_NK];             /* profile = 1: launches per class */
-    double matvec_bytes;                    /* algorithmic bytes moved by the Newton / CG
-                                               matvec launches of this gamma (each launch:
-                                               read V once, write the output once, the
-                                               incidence lists, and the per-edge Jacobian
-                                               payload of edges with P != I) */
-    int64_t matvec_launches;                /* matvec launches that did work (launches
-                                               issued after CG convergence return at once
-                                               and are timed in class CCM_K_OTHER) */
+    double kern_ms[CCM_NK];                 /* profile != 0: summed kernel time per class */
+    int64_t kern_calls[CCM_NK];             /* profile != 0: launches per class */
+    double matvec_bytes;                    /* profile != 0: algorithmic bytes of the timed
+                                               Newton / CG matvec launches that did work
+                                               (each launch: read V once, write the output
+                                               once, the incidence entries with their vertex
+                                               ids, and the Jacobian payload: per-incidence
+                                               scalars, lane masks, rows of Pi of edges with
+                                               P != I); 0 when profile = 0 */
+    int64_t matvec_launches;                /* the number of those launches (= kern_calls of
+                                               CCM_K_MATVEC; with profile = 2 one launch in
+                                               four is timed; launches issued after CG
+                                               convergence return at once and are counted
+                                               in class CCM_K_OTHER) */
 } ccm_stats;
 
 /* ---------------------------------------------------------------------------

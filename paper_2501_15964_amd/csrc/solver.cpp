@@ -50,40 +50,55 @@ enum Slot {
 // HIP-event timing of kernel classes (ccm_options.profile)
 struct Prof {
     bool on = false;
+    bool matvec_only = false;   // time only the Newton/CG matvec class,
+    int sample = 1;             // every sample-th launch of it
+    int64_t seen = 0;
+    bool last_recorded = false;
     hipStream_t s = nullptr;
     std::vector<hipEvent_t> ev;
     std::vector<int> cls;
+    std::vector<double> pbytes;  // algorithmic bytes of each timed launch
     size_t used = 0;
     double ms[CCM_NK] = {0};
     int64_t calls[CCM_NK] = {0};
+    double bytes[CCM_NK] = {0};
     int open_cls = -1;
+    double open_bytes = 0;
     ~Prof() {
         for (auto e : ev) (void)hipEventDestroy(e);
     }
-    void begin(int c) {
-        if (!on) return;
+    void begin(int c, double b) {
+        last_recorded = false;
+        if (!on || (matvec_only && c != CCM_K_MATVEC)) return;
+        if (matvec_only && (seen++ % sample) != 0) return;
         if (used + 2 > ev.size()) {
             for (int k = 0; k < 64; ++k) {
                 hipEvent_t e;
                 if (hipEventCreate(&e) == hipSuccess) ev.push_back(e);
             }
             cls.resize(ev.size() / 2 + 1);
+            pbytes.resize(ev.size() / 2 + 1);
         }
         if (used + 2 > ev.size()) return;
         (void)hipEventRecord(ev[used], s);
         open_cls = c;
+        open_bytes = b;
     }
     void end() {
         if (!on || open_cls < 0) return;
         (void)hipEventRecord(ev[used + 1], s);
         cls[used / 2] = open_cls;
+        pbytes[used / 2] = open_bytes;
         used += 2;
         open_cls = -1;
+        last_recorded = true;
     }
     // Pairs carry ids base + local index, so they can be reclassified or
     // harvested while later pairs are still in flight.
     size_t base = 0;
-    int64_t last_pair() const { return on && used >= 2 ? int64_t(base + used / 2) - 1 : -1; }
+    int64_t last_pair() const {
+        return on && last_recorded && used >= 2 ? int64_t(base + used / 2) - 1 : -1;
+    }
     int64_t next_pair() const { return int64_t(base + used / 2); }
     void reclass(int64_t id, int c) {
         if (!on || id < int64_t(base)) return;
@@ -101,6 +116,7 @@ struct Prof {
             if (hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]) == hipSuccess) {
                 ms[cls[k]] += t;
                 calls[cls[k]] += 1;
+                bytes[cls[k]] += pbytes[k];
             }
         }
         const size_t rem = have - np;
@@ -108,6 +124,7 @@ struct Prof {
             std::swap(ev[2 * r], ev[2 * (np + r)]);
             std::swap(ev[2 * r + 1], ev[2 * (np + r) + 1]);
             cls[r] = cls[np + r];
+            pbytes[r] = pbytes[np + r];
         }
         used = rem * 2;
         base += np;
@@ -121,12 +138,16 @@ struct Prof {
             ms[c] = 0;
             calls[c] = 0;
         }
+        // algorithmic bytes of exactly the matvec launches that were timed
+        st.matvec_bytes = bytes[CCM_K_MATVEC];
+        st.matvec_launches = st.kern_calls[CCM_K_MATVEC];
+        for (double& b : bytes) b = 0;
     }
 };
 
 struct Timed {
     Prof& p;
-    Timed(Prof& pr, int c) : p(pr) { p.begin(c); }
+    Timed(Prof& pr, int c, double bytes = 0.0) : p(pr) { p.begin(c, bytes); }
     ~Timed() { p.end(); }
 };
 
@@ -177,8 +198,6 @@ struct Solver::Impl {
     // ADMM state validity
     bool admm_state = false;
     double last_bytes = 0;      // algorithmic bytes of one Newton matvec at the current state
-    int64_t matvec_work = 0;    // matvec launches that did work (this gamma)
-    double matvec_bytes_sum = 0;
     // batched mode
     const BatchSpec* batch = nullptr;
     double floor_scale = 1.0;               // inner gradient floor relative to tol
@@ -191,6 +210,8 @@ struct Solver::Impl {
         : g(graph), d(d_), n(graph.n), m(graph.m), N(graph.n * d_), M(graph.m * d_), qk(qk_),
           A(A_), s(s_), o(opt), tol(tol_), err(e) {
         prof.on = o.profile != 0;
+        prof.matvec_only = o.profile == 2;
+        prof.sample = o.profile == 2 ? 4 : 1;
         prof.s = s;
     }
     ~Impl() {
@@ -367,8 +388,9 @@ struct Solver::Impl {
             Timed t(prof, CCM_K_CGUPDATE);
             launch_cg_init(N, b, neg, Dv, cg, s);
         }
+        const double mv_bytes = mode == 0 ? last_bytes : lap_bytes();
         {
-            Timed t(prof, CCM_K_MATVEC);
+            Timed t(prof, CCM_K_MATVEC, mv_bytes);
             cg.nparts_mv = launch_matvec(g, d, qk, mode, cg.u, Pic, p, gamma, sigma, 1.0, nullptr,
                                          cg.w, cg.wu[0], CgSkip{}, s);
         }
@@ -400,7 +422,7 @@ struct Solver::Impl {
                 }
                 q.upd.push_back(prof.last_pair());
                 {
-                    Timed t(prof, CCM_K_MATVEC);
+                    Timed t(prof, CCM_K_MATVEC, mv_bytes);
                     CgSkip sk;
                     sk.rr_partials = cg.upd[(j + 1) & 1];
                     sk.nparts = cg.nparts;
@@ -449,11 +471,6 @@ struct Solver::Impl {
         hflag[0] = done ? 1 : 0;
         hflag[1] = done ? done_at : j;
         iters = hflag[0] ? hflag[1] : j;
-        // matvec launches that did work: the initial one plus one per
-        // iteration whose residual was still above the threshold
-        const int work = hflag[0] ? std::max(1, hflag[1]) : 1 + j;
-        matvec_work += work;
-        matvec_bytes_sum += double(work) * (mode == 0 ? last_bytes : lap_bytes());
         return CCM_OK;
     }
 
@@ -647,7 +664,7 @@ struct Solver::Impl {
                                sigma, nullptr, ps.as<double>(), s);
             }
             {
-                Timed t(prof, CCM_K_MATVEC);
+                Timed t(prof, CCM_K_MATVEC, lap_bytes());
                 launch_matvec(g, d, qk, 1, X, nullptr, Payload{}, gamma, sigma, 1.0, nullptr, T,
                               pm2.as<double>(), CgSkip{}, s);
             }
@@ -900,10 +917,6 @@ ccm_status Solver::run_path(const double* gammas, int T, const double* Xw, const
         st.f_p = res[4];
         st.f_d = res[5];
         st.sigma = I.sigma;
-        st.matvec_bytes = I.matvec_bytes_sum;
-        st.matvec_launches = I.matvec_work;
-        I.matvec_bytes_sum = 0;
-        I.matvec_work = 0;
         I.prof.take(st);
         if (stats) stats[t] = st;
     }

@@ -216,6 +216,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter_chunk(DevGraph g, int d, Sca
                                                           const double* __restrict__ Z, Payload pl,
                                                           double* __restrict__ partials) {
     constexpr int U = Unroll<NPER>::US;
+    constexpr int NM = chunk_of<LPR, NPER>() / LPR > 0 ? chunk_of<LPR, NPER>() / LPR : 1;
+    constexpr bool PF = NM <= 4;  // chunk data fits a few registers per lane
     const int gl = (threadIdx.x & 63) % LPR;
     constexpr int GPB = kBlock / LPR;
     const int CW = 2 * d;
@@ -223,6 +225,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter_chunk(DevGraph g, int d, Sca
     for (int64_t c = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; c < g.nchunks;
          c += int64_t(gridDim.x) * GPB) {
         const ChunkCtx cx = chunk_ctx(g, c);
+        ChunkMeta<LPR, PF ? NM : 1> cm;
+        if constexpr (PF) chunk_meta_load<LPR, NM, Q, DIAG>(g, cx.cs, cx.ce, gl, pl, cm);
         int64_t vcur = -1;
         bool first = true;
         double acc[NPER], dg[NPER], xr[NPER], ar[NPER];
@@ -254,7 +258,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter_chunk(DevGraph g, int d, Sca
             Meta mt[U];
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (p0 + u < cx.ce) mt[u] = load_meta<Q, DIAG>(g, p0 + u, pl);
+                if (p0 + u < cx.ce) {
+                    if constexpr (PF)
+                        mt[u] = chunk_meta_get<LPR, NM, Q, DIAG, false>(cm, int(p0 + u - cx.cs));
+                    else
+                        mt[u] = load_meta<Q, DIAG>(g, p0 + u, pl);
+                }
             double zr[U][NPER];
             uint32_t lb[U];
 #pragma unroll
