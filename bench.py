@@ -52,9 +52,10 @@ WORKLOADS = {
                          desc="n=200 d=2 4 blobs, k=10 w=exp(-0.5 d^2), q=2, 10 gammas "
                               "[1e-3,1e1], SSNAL to KKT 1e-6"),
     "images784_n100000": dict(gen="images784", kw=dict(), k=10, phi=0.0, q=2.0,
-                              gammas=(-3.0, 1.0, 15), tol=1e-6,
-                              desc="n=100000 d=784 10 image classes quantised to k/255, k=10, "
-                                   "q=2, 15 gammas [1e-3,1e1], SSNAL to KKT 1e-6"),
+                              gammas=(-3.0, 1.0, 15), tol=1e-6, codes=1.0 / 255.0,
+                              desc="n=100000 d=784 10 image classes quantised to k/255, k=10 "
+                                   "graph from exact integer distances of the 8-bit codes "
+                                   "(int8 MFMA), q=2, 15 gammas [1e-3,1e1], SSNAL to KKT 1e-6"),
 }
 
 METRIC = "path wall-time @KKT 1e-6 + edge-op HBM GB/s %peak; plain vs batched/adjoint"
@@ -65,10 +66,12 @@ def log(*a):
 
 
 def make_points(wl):
+    """(A, K): the points, and their 8-bit codes when the workload's graph is
+    built from them (else None)."""
     import synthdata
     gen = getattr(synthdata, wl["gen"])
     out = gen(**wl["kw"])
-    return out[0]
+    return out[0], (out[2] if wl.get("codes") else None)
 
 
 def traffic_record(kernel_key):
@@ -90,10 +93,11 @@ def traffic_record(kernel_key):
     return rec
 
 
-def cpu_baseline(A_np, wl, budget_s=20.0):
+def cpu_baseline(A_np, K_np, wl, graph, budget_s=20.0):
     """The oracle on a bounded sample: k-NN rows and an evenly spaced subset
-    of the gammas (each warm-started from the previous sampled gamma),
-    scaled to one full step."""
+    of the gammas (each warm-started from the previous sampled gamma), scaled
+    to one full step.  The solve sample runs on `graph` (the step's own graph,
+    copied to the host; building it is not part of the sample)."""
     import oracle
     try:
         from threadpoolctl import threadpool_limits
@@ -103,23 +107,25 @@ def cpu_baseline(A_np, wl, budget_s=20.0):
     n = A_np.shape[0]
     k = wl["k"]
     # k-NN: a sample of query rows, scaled by n / rows
-    rows = np.arange(0, n, max(1, n // 200))
+    nrows = 200 if n * A_np.shape[1] <= 2e7 else 8
+    rows = np.arange(0, n, max(1, n // nrows))
     t0 = time.perf_counter()
-    oracle.knn_brute(A_np, k, rows=rows)
+    if K_np is not None:
+        oracle.knn_brute_u8(K_np, k, rows=rows, block=1)
+    else:
+        oracle.knn_brute(A_np, k, rows=rows)
     t_knn = (time.perf_counter() - t0) * n / len(rows)
-    # graph for the solve sample (built by the oracle itself, untimed)
-    src, dst, w, phi, _, _ = oracle.knn_graph(A_np, k, wl["phi"] if wl["phi"] > 0 else None)
+    src, dst, w = graph
     lo, hi, cnt = wl["gammas"]
     gam = np.logspace(lo, hi, int(cnt))
     stride = 5 if cnt >= 10 else 1
     sample = gam[::stride]
-    X = U = sig = None
+    X = U = None
     t_solve = 0.0
     done = 0
     for g in sample:
         t0 = time.perf_counter()
-        X, U, sig, info = oracle.ssnal(A_np, src, dst, w, g, wl["q"], wl["tol"], X0=X, U0=U,
-                                       sigma=sig)
+        X, U, _, info = oracle.ssnal(A_np, src, dst, w, g, wl["q"], wl["tol"], X0=X, U0=U)
         t_solve += time.perf_counter() - t0
         done += 1
         if t_solve > budget_s:
@@ -216,12 +222,13 @@ def main():
     import paper_2501_15964_amd as ccm
 
     wl = WORKLOADS[args.workload]
-    A_np = make_points(wl)
+    A_np, K_np = make_points(wl)
     n, d = A_np.shape
     lo, hi, cnt = wl["gammas"]
     gammas = np.logspace(lo, hi, int(cnt))
     dev = torch.device("cuda:0")
     A = torch.from_numpy(A_np).to(dev)
+    K = torch.from_numpy(K_np).to(dev) if K_np is not None else None
     torch.cuda.synchronize()
     # timed steps: HIP events around the Newton/CG matvec launches only (profile
     # level 2), which the roofline figure needs; one extra untimed step with
@@ -231,11 +238,14 @@ def main():
 
     def step(o=opts):
         t0 = time.perf_counter()
-        src, dst, w, phi = ccm.ccm_build_knn_graph(A, wl["k"], wl["phi"])
+        if K is not None:
+            src, dst, w, phi = ccm.ccm_build_knn_graph_u8(K, wl["codes"], wl["k"], wl["phi"])
+        else:
+            src, dst, w, phi = ccm.ccm_build_knn_graph(A, wl["k"], wl["phi"])
         t1 = time.perf_counter()
         out = ccm.ccm_solve_path(A, src, dst, w, gammas, wl["q"], wl["tol"], opts=o)
         t2 = time.perf_counter()
-        return out, (t1 - t0), (t2 - t1), int(src.numel()), phi
+        return out, (t1 - t0), (t2 - t1), int(src.numel()), phi, (src, dst, w)
 
     for i in range(args.warmup):
         step()
@@ -250,7 +260,7 @@ def main():
     elapsed = time.perf_counter() - t_start
     ms_per_step = 1000.0 * elapsed / args.steps
 
-    out, _, _, m, phi = results[-1]
+    out, _, _, m, phi, graph_dev = results[-1]
     kkt_max = float(np.max(out["kkt"][:, :3]))
     status = [int(s) for s in out["status"]]
     knn_ms = 1000.0 * float(np.mean([r[1] for r in results]))
@@ -333,7 +343,8 @@ def main():
         rec["batched"] = batched_leg(ccm, torch, args.batched_count, args.batched_budget)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
-        rec["cpu_baseline"] = cpu_baseline(A_np, wl)
+        graph = tuple(t.cpu().numpy() for t in graph_dev)
+        rec["cpu_baseline"] = cpu_baseline(A_np, K_np, wl, graph)
     print(json.dumps(rec))
 
 

@@ -1,0 +1,177 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times, on outputs the oracle can check one by one or through properties that
+hold at any size (GPU).
+
+* k-NN graphs: the neighbour lists of sampled rows (exact FP64 for the
+  n = 1e4 mixture, exact integers for the n = 1e5 quantised images), every
+  sampled graph edge justified by one endpoint's list, weights
+  exp(-phi d^2) of the oracle's d^2.
+* the n = 1e4, q = 2 path: the oracle's KKT evaluator certifies the GPU's
+  (X, U) at sampled gammas, labels equal the oracle's cluster rule on the
+  GPU's X, and the centroid is kept up to the certified residual.
+* the adjoint at n = 2e4: one directional central difference of tight solves.
+* batched instances at their full sizes (two per (q, d) group): every
+  instance converged, X within 1e-5 of the library's own tight (1e-10)
+  single-instance solve, and for the four smallest, within 1e-5 of an oracle
+  solve at 1e-9 started from the batched X.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthdata
+from oracle import operators as ops
+from oracle.graph import sq_dists_rows
+from gpu_util import need_gpu, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_rows(src, dst, w, phi, rows, nbr, d2):
+    """The GPU graph holds the oracle's k nearest of every sampled row with
+    weight exp(-phi d2)."""
+    pos = {e: i for i, e in enumerate(zip(src.tolist(), dst.tolist()))}
+    for r, i in enumerate(rows):
+        for j, dd in zip(nbr[r].tolist(), d2[r].tolist()):
+            e = (min(int(i), j), max(int(i), j))
+            assert e in pos, (int(i), j)
+            assert np.isclose(w[pos[e]], np.exp(-phi * dd), rtol=1e-14, atol=0)
+
+
+def _knn_rows_f64(A, rows, k):
+    D = sq_dists_rows(A, rows)
+    D[np.arange(len(rows)), rows] = np.inf
+    order = np.argsort(D, axis=1, kind="stable")[:, :k]
+    return order, np.take_along_axis(D, order, axis=1)
+
+
+def test_knn_mixture64_n10000_sampled_rows():
+    torch, ccm = need_gpu()
+    A, _ = synthdata.mixture64()
+    src, dst, w, phi = ccm.ccm_build_knn_graph(dev(A), 10, 0.0)
+    src, dst, w = host(src), host(dst), host(w)
+    n = A.shape[0]
+    assert np.all(src < dst) and np.all(np.diff(src.astype(np.int64) * n + dst) > 0)
+    rng = np.random.default_rng(900)
+    rows = np.sort(rng.choice(n, 48, replace=False))
+    nbr, d2 = _knn_rows_f64(A, rows, 10)
+    _check_rows(src, dst, w, phi, rows, nbr, d2)
+    # sampled edges: one endpoint lists the other among its 10 nearest
+    es = rng.choice(len(src), 40, replace=False)
+    for e in es:
+        i, j = int(src[e]), int(dst[e])
+        ni, _ = _knn_rows_f64(A, np.array([i]), 10)
+        nj, _ = _knn_rows_f64(A, np.array([j]), 10)
+        assert j in ni[0] or i in nj[0], (i, j)
+    # every vertex has at least its own 10 neighbours
+    deg = np.bincount(np.r_[src, dst], minlength=n)
+    assert deg.min() >= 10
+
+
+def test_knn_u8_images784_n100000_sampled_rows():
+    torch, ccm = need_gpu()
+    A, _, K = synthdata.images784()
+    src, dst, w, phi = ccm.ccm_build_knn_graph_u8(dev(K), 1.0 / 255.0, 10, 0.0)
+    src, dst, w = host(src), host(dst), host(w)
+    n = K.shape[0]
+    rng = np.random.default_rng(901)
+    rows = np.sort(rng.choice(n, 6, replace=False))
+    nbr, D = oracle.knn_brute_u8(K, 10, rows=rows, block=1)
+    d2 = D.astype(np.float64) * (1.0 / 255.0) * (1.0 / 255.0)
+    _check_rows(src, dst, w, phi, rows, nbr, d2)
+    deg = np.bincount(np.r_[src, dst], minlength=n)
+    assert deg.min() >= 10
+
+
+def test_path_mixture64_n10000_certified():
+    torch, ccm = need_gpu()
+    A, _ = synthdata.mixture64()
+    n = A.shape[0]
+    Ad = dev(A)
+    src, dst, w, phi = ccm.ccm_build_knn_graph(Ad, 10, 0.0)
+    gammas = np.logspace(-3, 2, 20)
+    out = ccm.ccm_solve_path(Ad, src, dst, w, gammas, 2.0, 1e-6, want_U=True)
+    src, dst, w = host(src), host(dst), host(w)
+    assert all(int(s) == 0 for s in out["status"])
+    B = oracle.incidence(src, dst, n)
+    S = oracle.fusion_scale(A)
+    for t in (0, 7, 13, 14, 19):
+        X = host(out["X"][t])
+        U = host(out["U"][t])
+        res = ops.kkt_residuals(X, U, A, B, gammas[t] * w, 2.0)
+        assert res["kkt"] <= 1e-6 * 1.0001, (t, res)
+        # centroid: sum(X - A) = -B^T U summed over vertices = 0 up to R_D
+        drift = np.linalg.norm((X - A).sum(0)) / (1 + np.linalg.norm(A))
+        assert drift <= np.sqrt(n) * res["R_D"] + 1e-12, (t, drift)
+        # labels: the oracle's cluster rule on the GPU's X, unless an edge sits
+        # within rounding of the fusion threshold
+        nd = np.linalg.norm(X[src] - X[dst], axis=1)
+        thr = oracle.labels.FUSE_TOL * (1.0 + S)
+        if np.min(np.abs(nd - thr)) > 1e-9 * thr:
+            lab, nc = oracle.cluster_labels(X, src, dst, n, S)
+            assert np.array_equal(host(out["labels"][t]), lab), t
+            assert out["n_clusters"][t] == nc
+
+
+def test_vjp_mixture32_n20000_directional_difference():
+    torch, ccm = need_gpu()
+    A, _, T = synthdata.mixture32()
+    Ad = dev(A)
+    src, dst, w, phi = ccm.ccm_build_knn_graph(Ad, 10, 0.0)
+    g = 0.5
+
+    def solve(Ax):
+        o = ccm.ccm_solve_path(Ax, src, dst, w, [g], 2.0, 1e-11)
+        assert int(o["status"][0]) == 0
+        return host(o["X"][0]), o["labels"][0]
+
+    X, lab = solve(Ad)
+    dLdX = 2.0 * (X - T)
+    gA, gw, gg, iters = ccm.ccm_path_vjp(Ad, src, dst, w, g, dev(X), lab, dev(dLdX), tol=1e-12)
+    rng = np.random.default_rng(902)
+    D = rng.normal(size=A.shape)
+    # h balances the O(h^2) truncation against the solve error / h
+    h = 1e-4
+    Xp, lp = solve(dev(A + h * D))
+    Xm, lm = solve(dev(A - h * D))
+    assert np.array_equal(host(lp), host(lab)) and np.array_equal(host(lm), host(lab))
+    L = lambda Z: float(((Z - T) ** 2).sum())
+    fd = (L(Xp) - L(Xm)) / (2 * h)
+    an = float((host(gA) * D).sum())
+    assert abs(an - fd) <= 1e-5 * max(1.0, abs(fd)), (an, fd)
+
+
+def test_batched_full_size_instances_certified():
+    torch, ccm = need_gpu()
+    allinst = synthdata.instances(count=512)
+    # two instances per (q, d) group, at their full sizes
+    picked, seen = [], {}
+    for it in allinst:
+        key = (it["q"], it["d"])
+        if seen.get(key, 0) < 2:
+            picked.append(it)
+            seen[key] = seen.get(key, 0) + 1
+    devs = []
+    for it in picked:
+        Ad = dev(it["A"])
+        s, d_, w, _ = ccm.ccm_build_knn_graph(Ad, 10, 0.0)
+        devs.append(dict(A=Ad, src=s, dst=d_, w=w, q=it["q"]))
+    gammas = np.logspace(-3, 1, 10)
+    res = ccm.ccm_solve_path_batched(devs, gammas, 1e-6,
+                                     opts=ccm.ccm_default_options(time_budget_s=120))
+    small = sorted(range(len(picked)), key=lambda i: picked[i]["n"])[:4]
+    for i, (it, x, r) in enumerate(zip(picked, devs, res)):
+        assert np.all(r["status"] == 0), (it["n"], it["d"], it["q"], r["status"])
+        assert r["kkt"][:, :3].max() <= 1e-6 * 1.0001
+        # the same instance solved alone by the library, tightly
+        one = ccm.ccm_solve_path(x["A"], x["src"], x["dst"], x["w"], gammas, it["q"], 1e-10)
+        for t in (2, 9):
+            Xb, Xs = host(r["X"][t]), host(one["X"][t])
+            assert np.linalg.norm(Xb - Xs) / (1 + np.linalg.norm(Xs)) <= 1e-5, (t, it["n"])
+        if i in small:
+            # the oracle from the batched X at a tight tolerance stays within 1e-5
+            src, dst, w = host(x["src"]), host(x["dst"]), host(x["w"])
+            t = 9
+            Xt = host(r["X"][t])
+            Xo, _, _, _ = oracle.ssnal(it["A"], src, dst, w, gammas[t], it["q"], 1e-9, X0=Xt)
+            assert np.linalg.norm(Xt - Xo) / (1 + np.linalg.norm(Xo)) <= 1e-5, (t, it["n"])
