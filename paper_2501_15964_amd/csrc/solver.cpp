@@ -179,6 +179,7 @@ struct Solver::Impl {
     // edge buffers
     DevMem bU, bPi, bPit, bZ, bL, bQ, bZold;
     DevMem ip0, ip1, lb0, lb1;  // Jacobian payload (current, trial)
+    int cg_pred[2] = {8, 8};    // predicted CG iterations (Newton, Laplacian systems)
     DevMem fused, parent, rank, ltemp;
     size_t ltemp_bytes = 0;
     // reductions
@@ -398,7 +399,12 @@ struct Solver::Impl {
         // enqueued before the host waits for chunk k's status, so the host's
         // decision overlaps device work.  Launches issued after convergence
         // return at once (device-side flag) and are timed as "other".
+        // The first chunk is sized from the previous solve's iteration count
+        // (consecutive Newton systems need similar counts), later ones are
+        // half a chunk: fewer launches are wasted after convergence.
         const int chunk = std::max(1, o.cg_chunk);
+        const int first = std::max(2, std::min(2 * chunk, cg_pred[mode & 1]));
+        const int later = std::max(2, chunk / 2);
         int j = 0;
         struct Pending {
             int j0 = 0, j1 = 0;
@@ -411,11 +417,11 @@ struct Solver::Impl {
         P[1].hf = hflag + 4;
         P[0].e = cg_ev[0];
         P[1].e = cg_ev[1];
-        auto issue = [&](Pending& q) -> ccm_status {
+        auto issue = [&](Pending& q, int count) -> ccm_status {
             q.j0 = j;
             q.upd.clear();
             q.mv.clear();
-            for (int c = 0; c < chunk && j < o.cg_max_iter; ++c, ++j) {
+            for (int c = 0; c < count && j < o.cg_max_iter; ++c, ++j) {
                 {
                     Timed t(prof, CCM_K_CGUPDATE);
                     launch_cg_update(N, j, Dv, cg, thr, s);
@@ -442,10 +448,10 @@ struct Solver::Impl {
         int cur = 0;
         bool done = false;
         int done_at = 0;
-        CHK(issue(P[0]));
+        CHK(issue(P[0], first));
         while (true) {
             const bool more = j < o.cg_max_iter;
-            if (more) CHK(issue(P[cur ^ 1]));
+            if (more) CHK(issue(P[cur ^ 1], later));
             HIPCHK(hipEventSynchronize(P[cur].e));
             const Pending& q = P[cur];
             if (q.hf[0]) {
@@ -471,6 +477,7 @@ struct Solver::Impl {
         hflag[0] = done ? 1 : 0;
         hflag[1] = done ? done_at : j;
         iters = hflag[0] ? hflag[1] : j;
+        cg_pred[mode & 1] = iters + 1;
         return CCM_OK;
     }
 
