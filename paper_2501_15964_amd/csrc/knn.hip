@@ -3,10 +3,11 @@
 // Squared distances are accumulated feature by feature in ascending order
 // with separately rounded products and sums (no fused multiply-add), so every
 // d^2 is bit-defined and the neighbour order (d^2, index) is reproducible.
-// A block owns 128 query rows (one per thread, held transposed in LDS) and
-// streams tiles of 32 candidate rows through LDS; each thread keeps its best
-// KP candidates in registers with a fixed-shape insertion network.  Candidate
-// columns are split over blockIdx.y; a second pass merges the partial lists.
+// A block computes 64 x 64 tiles of distances (a 4 x 4 register tile per
+// thread, query and candidate features staged through LDS 16 at a time),
+// writes each tile to LDS, and 4 threads per query row scan it into partial
+// top-KP lists (one per quarter of the tile columns).  Candidate columns are
+// split over blockIdx.y; a second pass merges the partial lists.
 #include <hipcub/hipcub.hpp>
 
 #include "knn.hpp"
@@ -14,9 +15,9 @@
 namespace ccm {
 namespace {
 
-constexpr int kQT = 128;  // query rows per block
-constexpr int kCT = 32;   // candidate rows per tile
-constexpr int kDK = 64;   // features per LDS chunk
+constexpr int kQT = 64;   // query rows per block
+constexpr int kCT = 64;   // candidate rows per tile
+constexpr int kDK = 16;   // features per LDS chunk
 
 __device__ __forceinline__ bool knn_less(double da, int ja, double db, int jb) {
     return da < db || (da == db && ja < jb);
@@ -46,18 +47,22 @@ __device__ __forceinline__ void knn_insert(double (&bd)[KP], int (&bi)[KP], doub
 }
 
 template <int KP>
-__global__ __launch_bounds__(kQT) void k_knn_partial(const double* __restrict__ A, int64_t n, int d,
-                                                     int64_t cols_per_split,
-                                                     double* __restrict__ pd,
-                                                     int* __restrict__ pi) {
+__global__ __launch_bounds__(kBlock) void k_knn_partial(const double* __restrict__ A, int64_t n,
+                                                        int d, int64_t cols_per_split,
+                                                        double* __restrict__ pd,
+                                                        int* __restrict__ pi) {
     __shared__ double Qs[kDK][kQT];
-    __shared__ double Cs[kCT][kDK + 1];
+    __shared__ double Cs[kDK][kCT];
+    __shared__ double Ds[kQT][kCT + 1];
     const int tid = threadIdx.x;
+    const int tx = tid % 16, ty = tid / 16;  // candidates 4 tx.., queries 4 ty..
     const int64_t q0 = int64_t(blockIdx.x) * kQT;
-    const int64_t qi = q0 + tid;
     const int64_t c_begin = int64_t(blockIdx.y) * cols_per_split;
     int64_t c_end = c_begin + cols_per_split;
     if (c_end > n) c_end = n;
+    // scan role: query row tid / 4, quarter tid % 4 of the tile columns
+    const int srow = tid >> 2, quarter = tid & 3;
+    const int64_t qi = q0 + srow;
     double bd[KP];
     int bi[KP];
 #pragma unroll
@@ -66,21 +71,23 @@ __global__ __launch_bounds__(kQT) void k_knn_partial(const double* __restrict__ 
         bi[p] = 0x7fffffff;
     }
     for (int64_t c0 = c_begin; c0 < c_end; c0 += kCT) {
-        double acc[kCT];
+        double acc[4][4];
 #pragma unroll
-        for (int c = 0; c < kCT; ++c) acc[c] = 0.0;
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
         for (int k0 = 0; k0 < d; k0 += kDK) {
             const int dk = (d - k0) < kDK ? (d - k0) : kDK;
             __syncthreads();
-            for (int e = tid; e < kQT * kDK; e += kQT) {
+            for (int e = tid; e < kQT * kDK; e += kBlock) {
                 const int t = e / kDK, k = e % kDK;
                 const int64_t row = q0 + t;
                 Qs[k][t] = (row < n && k < dk) ? A[row * d + k0 + k] : 0.0;
             }
-            for (int e = tid; e < kCT * kDK; e += kQT) {
+            for (int e = tid; e < kCT * kDK; e += kBlock) {
                 const int c = e / kDK, k = e % kDK;
                 const int64_t row = c0 + c;
-                Cs[c][k] = (row < c_end && k < dk) ? A[row * d + k0 + k] : 0.0;
+                Cs[k][c] = (row < c_end && k < dk) ? A[row * d + k0 + k] : 0.0;
             }
             __syncthreads();
             {
@@ -88,26 +95,38 @@ __global__ __launch_bounds__(kQT) void k_knn_partial(const double* __restrict__ 
                 // into fused multiply-adds, so each d^2 is bit-defined
 #pragma clang fp contract(off)
                 for (int k = 0; k < dk; ++k) {
-                    const double qv = Qs[k][tid];
+                    double qv[4], cv[4];
 #pragma unroll
-                    for (int c = 0; c < kCT; ++c) {
-                        const double df = qv - Cs[c][k];
-                        const double sq = df * df;
-                        acc[c] = acc[c] + sq;
+                    for (int i = 0; i < 4; ++i) qv[i] = Qs[k][ty * 4 + i];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) cv[j] = Cs[k][tx * 4 + j];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const double df = qv[i] - cv[j];
+                            const double sq = df * df;
+                            acc[i][j] = acc[i][j] + sq;
+                        }
                     }
                 }
             }
         }
-        if (qi < n) {
 #pragma unroll
-            for (int c = 0; c < kCT; ++c) {
-                const int64_t j = c0 + c;
-                if (j < c_end && j != qi) knn_insert<KP>(bd, bi, acc[c], int(j));
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) Ds[ty * 4 + i][tx * 4 + j] = acc[i][j];
+        __syncthreads();
+        if (qi < n) {
+            for (int cc = quarter * 16; cc < quarter * 16 + 16; ++cc) {
+                const int64_t j = c0 + cc;
+                if (j >= c_end || j == qi) continue;
+                knn_insert<KP>(bd, bi, Ds[srow][cc], int(j));
             }
         }
     }
     if (qi < n) {
-        const int64_t base = (int64_t(blockIdx.y) * n + qi) * KP;
+        const int64_t base = ((int64_t(blockIdx.y) * 4 + quarter) * n + qi) * KP;
 #pragma unroll
         for (int p = 0; p < KP; ++p) {
             pd[base + p] = bd[p];
@@ -345,10 +364,11 @@ __global__ __launch_bounds__(kBlock) void k_knn_u8(const signed char* __restrict
 template <int KP>
 void launch_knn(const double* A, int64_t n, int d, int k, int splits, int64_t cps, double* pd,
                 int* pi, int* nbr, double* nd2, hipStream_t s) {
-    dim3 grid(unsigned((n + kQT - 1) / kQT), unsigned(splits));
-    hipLaunchKernelGGL((k_knn_partial<KP>), grid, dim3(kQT), 0, s, A, n, d, cps, pd, pi);
-    hipLaunchKernelGGL((k_knn_merge<KP>), dim3(flat_grid(n)), dim3(kBlock), 0, s, n, k, splits,
-                       pd, pi, nbr, nd2);
+    const dim3 grid{unsigned((n + kQT - 1) / kQT), unsigned(splits), 1u};
+    hipLaunchKernelGGL((k_knn_partial<KP>), grid, dim3(kBlock), 0, s, A, n, d, cps, pd, pi);
+    // four partial lists (tile quarters) per split and row
+    hipLaunchKernelGGL((k_knn_merge<KP>), dim3(flat_grid(n)), dim3(kBlock), 0, s, n, k,
+                       splits * 4, pd, pi, nbr, nd2);
 }
 
 }  // namespace
@@ -371,8 +391,8 @@ ccm_status knn_graph(const double* A, int64_t n, int d, int k, double phi, int* 
     splits = (n + cps - 1) / cps;
     const int64_t cnt = n * k;
     DevMem pd, pi, nbr, nd2;
-    HIPCHK(pd.alloc(size_t(splits) * n * KP * 8, s));
-    HIPCHK(pi.alloc(size_t(splits) * n * KP * 4, s));
+    HIPCHK(pd.alloc(size_t(splits) * 4 * n * KP * 8, s));
+    HIPCHK(pi.alloc(size_t(splits) * 4 * n * KP * 4, s));
     HIPCHK(nbr.alloc(size_t(cnt) * 4, s));
     HIPCHK(nd2.alloc(size_t(cnt) * 8, s));
     switch (KP) {
