@@ -79,8 +79,8 @@ typedef struct {
     int32_t profile;       /* 1: time every kernel class with HIP events (ccm_stats.kern_*);
                               2: time only the Newton/CG matvec class (less host work);
                               0: off */
-    double sigma0;         /* initial penalty on a cold start; <= 0: method default
-                              (10 for SSNAL, 1 for ADMM) */
+    double sigma0;         /* initial penalty (SSNAL: of every gamma; ADMM: on a cold
+                              start); <= 0: default 1 */
     double sigma_max;      /* SSNAL penalty cap.  1e4 */
     double tau;            /* ADMM multiplier step.  1.618 */
     double time_budget_s;  /* wall-clock budget for the whole path; <= 0: none */

@@ -57,7 +57,7 @@ SSNAL_DEFAULTS = dict(
     max_outer=300,
     max_newton=60,
     cg_maxit=500,
-    sigma0=10.0,
+    sigma0=1.0,
     sigma_max=1e4,
     sigma_grow=2.0,
     rp_ratio=0.9,         # grow sigma only when R_P fell by less than 10%

@@ -202,7 +202,7 @@ ccm_status ccm_solve_path(const double* A, int64_t n, int64_t d, const int32_t* 
         return fail(CCM_E_INVALID, "unknown method");
     if (o.max_outer < 1 || o.max_newton < 1 || o.cg_max_iter < 1 || o.max_iter < 1)
         return fail(CCM_E_INVALID, "iteration limits must be >= 1");
-    if (o.sigma0 <= 0) o.sigma0 = (o.method == CCM_SSNAL) ? 10.0 : 1.0;
+    if (o.sigma0 <= 0) o.sigma0 = 1.0;
     if (!(o.sigma_max >= o.sigma0)) o.sigma_max = o.sigma0;
     if (!(o.tau > 0 && o.tau < 1.6181)) return fail(CCM_E_INVALID, "tau must be in (0, 1.618]");
     st = check_finite(A, n * d, stream, "A");
@@ -240,7 +240,7 @@ ccm_status ccm_solve_path_batched(const ccm_instance* inst_host, int32_t n_inst,
     o.method = CCM_SSNAL;
     if (o.max_outer < 1 || o.max_newton < 1 || o.cg_max_iter < 1)
         return fail(CCM_E_INVALID, "iteration limits must be >= 1");
-    if (o.sigma0 <= 0) o.sigma0 = 10.0;
+    if (o.sigma0 <= 0) o.sigma0 = 1.0;
     if (!(o.sigma_max >= o.sigma0)) o.sigma_max = o.sigma0;
     // group instances by (q, d)
     std::map<std::pair<int, int64_t>, std::vector<int>> groups;

@@ -7,11 +7,12 @@ hold at any size (GPU).
   sampled graph edge justified by one endpoint's list, weights
   exp(-phi d^2) of the oracle's d^2.
 * the n = 1e4, q = 2 path: the oracle's KKT evaluator certifies the GPU's
-  (X, U) at sampled gammas, labels equal the oracle's cluster rule on the
-  GPU's X, and the centroid is kept up to the certified residual.
+  (X, U) at sampled gammas, X is within 1e-5 of a tight (1e-11) solve,
+  labels equal the oracle's cluster rule on the GPU's X, and the centroid is
+  kept up to the certified residual.
 * the adjoint at n = 2e4: one directional central difference of tight solves.
-* batched instances at their full sizes (two per (q, d) group): every
-  instance converged, X within 1e-5 of the library's own tight (1e-10)
+* batched instances at their full sizes (two per (q, d) group, KKT 5e-7):
+  every instance converged, X within 1e-5 of the library's own tight (1e-10)
   single-instance solve, and for the four smallest, within 1e-5 of an oracle
   solve at 1e-9 started from the batched X.
 """
@@ -91,8 +92,10 @@ def test_path_mixture64_n10000_certified():
     src, dst, w, phi = ccm.ccm_build_knn_graph(Ad, 10, 0.0)
     gammas = np.logspace(-3, 2, 20)
     out = ccm.ccm_solve_path(Ad, src, dst, w, gammas, 2.0, 1e-6, want_U=True)
+    tight = ccm.ccm_solve_path(Ad, src, dst, w, gammas, 2.0, 1e-11)
     src, dst, w = host(src), host(dst), host(w)
     assert all(int(s) == 0 for s in out["status"])
+    assert all(int(s) == 0 for s in tight["status"])
     B = oracle.incidence(src, dst, n)
     S = oracle.fusion_scale(A)
     for t in (0, 7, 13, 14, 19):
@@ -100,6 +103,10 @@ def test_path_mixture64_n10000_certified():
         U = host(out["U"][t])
         res = ops.kkt_residuals(X, U, A, B, gammas[t] * w, 2.0)
         assert res["kkt"] <= 1e-6 * 1.0001, (t, res)
+        # X bar against the library's own tight solve (itself pinned to the
+        # oracle at small sizes)
+        Xs = host(tight["X"][t])
+        assert np.linalg.norm(X - Xs) / np.linalg.norm(Xs) <= 1e-5, t
         # centroid: sum(X - A) = -B^T U summed over vertices = 0 up to R_D
         drift = np.linalg.norm((X - A).sum(0)) / (1 + np.linalg.norm(A))
         assert drift <= np.sqrt(n) * res["R_D"] + 1e-12, (t, drift)
@@ -157,12 +164,16 @@ def test_batched_full_size_instances_certified():
         s, d_, w, _ = ccm.ccm_build_knn_graph(Ad, 10, 0.0)
         devs.append(dict(A=Ad, src=s, dst=d_, w=w, q=it["q"]))
     gammas = np.logspace(-3, 1, 10)
-    res = ccm.ccm_solve_path_batched(devs, gammas, 1e-6,
+    # KKT 5e-7: at 1e-6 the relative KKT test (normalised by ||U||, large at
+    # large gamma) lets X drift up to ~1.1e-5 from the solution on some q = inf
+    # instances; at 5e-7 every instance measured within 7e-6
+    tol = 5e-7
+    res = ccm.ccm_solve_path_batched(devs, gammas, tol,
                                      opts=ccm.ccm_default_options(time_budget_s=120))
     small = sorted(range(len(picked)), key=lambda i: picked[i]["n"])[:4]
     for i, (it, x, r) in enumerate(zip(picked, devs, res)):
         assert np.all(r["status"] == 0), (it["n"], it["d"], it["q"], r["status"])
-        assert r["kkt"][:, :3].max() <= 1e-6 * 1.0001
+        assert r["kkt"][:, :3].max() <= tol * 1.0001
         # the same instance solved alone by the library, tightly
         one = ccm.ccm_solve_path(x["A"], x["src"], x["dst"], x["w"], gammas, it["q"], 1e-10)
         for t in (2, 9):
