@@ -2,6 +2,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <vector>
 
 #include "graph.hpp"
 
@@ -105,29 +106,6 @@ __global__ __launch_bounds__(kBlock) void k_epos(int64_t cnt, const Inc* __restr
         const int e = inc[p].e;
         if (e >= 0) epos[2 * int64_t(e)] = int(p);
         else epos[2 * int64_t(~e) + 1] = int(p);
-    }
-}
-
-// vertices finished by the fix-up pass: isolated, or cut by a chunk boundary
-__global__ __launch_bounds__(kBlock) void k_special_flags(int64_t n, int C,
-                                                          const int* __restrict__ ptr,
-                                                          int* __restrict__ flag) {
-    for (int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x; v < n;
-         v += int64_t(gridDim.x) * kBlock) {
-        const int64_t b = ptr[v], e = ptr[v + 1];
-        flag[v] = (e == b) || (b / C != (e - 1) / C) ? 1 : 0;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_special_emit(int64_t n, const int* __restrict__ ptr,
-                                                         const int* __restrict__ flag,
-                                                         const int* __restrict__ pos,
-                                                         int4* __restrict__ special,
-                                                         int* __restrict__ count) {
-    for (int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x; v < n;
-         v += int64_t(gridDim.x) * kBlock) {
-        if (flag[v]) special[pos[v]] = int4{int(v), ptr[v], ptr[v + 1], 0};
-        if (v == n - 1) count[0] = pos[v] + flag[v];
     }
 }
 
@@ -261,7 +239,7 @@ ccm_status membership_build(const int* labels, int64_t n, int64_t K, int d, hipS
     out.g.inc_ptr = out.inc_ptr.as<int>();
     out.g.inc = out.inc.as<Inc>();
     out.g.irow = out.irow.as<int>();
-    return build_chunks(d, s, out, err);
+    return build_windows(d, s, out, err);
 }
 
 ccm_status graph_canonical_count(const int* src, const int* dst, const double* w, int64_t m,
@@ -343,46 +321,55 @@ ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t 
     out.g.epos = out.epos.as<int>();
     out.g.max_deg = md;
     out.g.nent = cnt;
-    return build_chunks(d, s, out, err);
+    return build_windows(d, s, out, err);
 }
 
-ccm_status build_chunks(int d, hipStream_t s, OwnedGraph& out, std::string& err) {
-    // balanced chunks of the incidence array and the fix-up vertex list
+ccm_status build_windows(int d, hipStream_t s, OwnedGraph& out, std::string& err) {
+    // Vertex-aligned windows of the incidence array, packed greedily on the
+    // host: consecutive whole vertices while the window holds at most S
+    // entries; a vertex with more than S entries (a hub) forms a window of
+    // its own.  Then the isolated vertices.
     const int64_t n = out.g.n;
     const int64_t cnt = out.g.nent;
     if (cnt > 0 && (!out.g.inc || !out.g.irow || !out.g.inc_ptr)) {
         err = "internal: incidence lists incomplete (entries, vertex ids or offsets missing)";
         return CCM_E_HIP;
     }
-    const int C = chunk_for(d);
-    const int64_t nch = (cnt + C - 1) / C;
-    out.g.chunk = C;
-    out.g.nchunks = nch;
-    HIPCHK(out.special.alloc(size_t(n) * 16, s));
-    HIPCHK(out.carry.alloc(size_t(std::max<int64_t>(nch, 1)) * 2 * 2 * size_t(d) * 8, s));
-    {
-        DevMem flag, pos, temp2, count;
-        HIPCHK(flag.alloc(size_t(n) * 4, s));
-        HIPCHK(pos.alloc(size_t(n) * 4, s));
-        HIPCHK(count.alloc(4, s));
-        hipLaunchKernelGGL(k_special_flags, dim3(flat_grid(n)), dim3(kBlock), 0, s, n, C,
-                           out.g.inc_ptr, flag.as<int>());
-        size_t b = 0;
-        HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, b, flag.as<int>(), pos.as<int>(), int(n),
-                                                s));
-        HIPCHK(temp2.alloc(b, s));
-        HIPCHK(hipcub::DeviceScan::ExclusiveSum(temp2.p, b, flag.as<int>(), pos.as<int>(), int(n),
-                                                s));
-        hipLaunchKernelGGL(k_special_emit, dim3(flat_grid(n)), dim3(kBlock), 0, s, n,
-                           out.g.inc_ptr, flag.as<int>(), pos.as<int>(), out.special.as<int4>(),
-                           count.as<int>());
-        int ns = 0;
-        HIPCHK(hipMemcpyAsync(&ns, count.p, 4, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        out.g.nspecial = ns;
+    const int64_t S = window_for(d);
+    std::vector<int> ptr(size_t(n) + 1);
+    HIPCHK(hipMemcpyAsync(ptr.data(), out.g.inc_ptr, ptr.size() * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<int2> win;
+    std::vector<int> iso;
+    win.reserve(size_t(cnt / S + 2));
+    int64_t ws = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t b = ptr[v], e = ptr[v + 1];
+        if (e == b) {
+            iso.push_back(int(v));
+            continue;
+        }
+        if (e - ws > S && b > ws) {
+            win.push_back(int2{int(ws), int(b)});
+            ws = b;
+        }
     }
-    out.g.special = out.special.as<int4>();
-    out.g.carry = out.carry.as<double>();
+    if (cnt > ws) win.push_back(int2{int(ws), int(cnt)});
+    // longest first, ties in entry order
+    std::stable_sort(win.begin(), win.end(),
+                     [](const int2& a, const int2& b) { return a.y - a.x > b.y - b.x; });
+    HIPCHK(out.win.alloc(std::max<size_t>(win.size(), 1) * 8, s));
+    HIPCHK(out.iso.alloc(std::max<size_t>(iso.size(), 1) * 4, s));
+    if (!win.empty())
+        HIPCHK(hipMemcpyAsync(out.win.p, win.data(), win.size() * 8, hipMemcpyHostToDevice, s));
+    if (!iso.empty())
+        HIPCHK(hipMemcpyAsync(out.iso.p, iso.data(), iso.size() * 4, hipMemcpyHostToDevice, s));
+    // the host vectors die on return: wait for the copies
+    HIPCHK(hipStreamSynchronize(s));
+    out.g.nwin = int64_t(win.size());
+    out.g.niso = int64_t(iso.size());
+    out.g.win = out.win.as<int2>();
+    out.g.iso = out.iso.as<int>();
     return CCM_OK;
 }
 

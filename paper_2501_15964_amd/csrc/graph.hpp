@@ -32,7 +32,7 @@ struct DevMem {
 
 struct OwnedGraph {
     DevGraph g;
-    DevMem src, dst, w, inc_ptr, inc, irow, epos, special, carry;
+    DevMem src, dst, w, inc_ptr, inc, irow, epos, win, iso;
 };
 
 // Builds `out` from caller edges for rows of d values.  With
@@ -44,9 +44,9 @@ ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t 
                        int d, bool require_canonical, hipStream_t s, OwnedGraph& out,
                        std::string& err);
 
-// Chunk decomposition (special, carry) of out.g's incidence lists for rows
-// of d values; needs out.g.n, nent, inc_ptr.  Synchronises s.
-ccm_status build_chunks(int d, hipStream_t s, OwnedGraph& out, std::string& err);
+// Window split (win, iso) of out.g's incidence lists for rows of d values;
+// needs out.g.n, nent, inc_ptr, inc, irow.  Synchronises s.
+ccm_status build_windows(int d, hipStream_t s, OwnedGraph& out, std::string& err);
 
 // Cluster membership lists as a graph for the vertex kernels: row c lists
 // the vertices with labels == c (labels in [0, K)), entries {vertex, 0}.

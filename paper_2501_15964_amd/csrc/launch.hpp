@@ -32,16 +32,6 @@ inline void dispatch_row(int d, F&& f) {
     else f(IC<64>{}, IC<16>{});
 }
 
-// values per lane of a whole-wave row layout (64 lanes): ceil(d / 64) rounded up
-template <class F>
-inline void dispatch_fix(int d, F&& f) {
-    if (d <= 64) f(IC<1>{});
-    else if (d <= 128) f(IC<2>{});
-    else if (d <= 256) f(IC<4>{});
-    else if (d <= 512) f(IC<8>{});
-    else f(IC<16>{});
-}
-
 template <class F>
 inline void dispatch_q(int qk, F&& f) {
     if (qk == kQ1) f(IC<kQ1>{});
@@ -100,23 +90,27 @@ struct DevGraph {
     const int* irow = nullptr;     // vertex of each incidence entry (2 m)
     const int* epos = nullptr;     // incidence positions of edge l: [2 l] at src, [2 l + 1] at dst
     int max_deg = 0;
-    // Balanced split of the incidence array for the vertex kernels: chunk c
-    // holds incidences [c C, (c + 1) C).  A vertex whose incidence range lies
-    // inside one chunk is finished by that chunk; a vertex cut by a chunk
-    // boundary leaves one partial row per chunk in `carry` (slot 0 when the
-    // chunk starts inside the vertex's range, else slot 1), summed in chunk
-    // order by a fix-up pass that also handles isolated vertices.
-    int64_t nent = 0;               // incidence entries (2 m for an edge graph)
-    int chunk = 16;                 // C
-    int64_t nchunks = 0;
-    const int4* special = nullptr;  // fix-up vertices {v, inc_ptr[v], inc_ptr[v + 1], 0}
-    int64_t nspecial = 0;
-    double* carry = nullptr;        // nchunks x 2 slots x (2 d) doubles
+    // Work split of the incidence array for the vertex kernels: window w holds
+    // the entries win[w] = {begin, end} of consecutive whole vertices, at most
+    // window_for(d) of them unless the window is a single hub vertex.  One
+    // workgroup takes a window; its row groups split the window's entries
+    // evenly, and a vertex cut between row groups is summed through LDS, in
+    // row-group order, by the group where it starts.  Windows are stored
+    // longest first (hubs start early).  Isolated vertices have no entries
+    // and are listed in `iso`.
+    int64_t nent = 0;            // incidence entries (2 m for an edge graph)
+    const int2* win = nullptr;   // nwin non-empty windows
+    int64_t nwin = 0;
+    const int* iso = nullptr;    // vertices without incidences
+    int64_t niso = 0;
 };
 
-// incidences per chunk: about one typical vertex for long rows, several
-// short vertices for short rows
+// incidences per row group of a window: about one typical vertex for long
+// rows, several short vertices for short rows
 inline int chunk_for(int d) { return d <= 64 ? 16 : d <= 256 ? 32 : 64; }
+
+// target entries per window: one chunk for each row group of a workgroup
+inline int64_t window_for(int d) { return int64_t(kBlock / lanes_per_row(d)) * chunk_for(d); }
 
 // ---- edge kernels (edge_kernels.hip) --------------------------------------
 // SSNAL edge pass: Y = U + sigma B X, Pi = Pi_C(Y), payload; partials per

@@ -3,20 +3,23 @@
 //
 // Both walk the vertex-major incidence array (entries sorted by vertex, each
 // vertex's entries in ascending edge order).  k-NN graphs are skewed (a few
-// hub vertices have tens of times the mean degree), so work is not split by
-// vertex but by equal chunks of C incidences: a row group takes one chunk,
-// finishes every vertex whose incidences all lie inside it, and leaves a
-// partial row for a vertex cut by a chunk boundary.  A fix-up pass sums those
-// partials in chunk order and finishes isolated vertices.  There are no
-// atomics and the summation order is fixed, so results are bit-reproducible.
-// An edge row is read by both of its endpoints.
+// hub vertices have tens of times the mean degree), so work is split by
+// entries, not by vertices: a workgroup takes a window of whole vertices and
+// its row groups split the window's entries evenly.  A row group finishes
+// every vertex whose entries lie inside its share; a vertex cut between row
+// groups leaves its later pieces in LDS, and the row group where it starts
+// adds them in row-group order after a barrier.  There are no atomics and
+// the summation order is fixed, so results are bit-reproducible.  An edge row
+// is read by both of its endpoints.
 //
 // Everything needed to issue an entry's row gathers (edge, other endpoint,
 // the entry's own vertex, the Jacobian scalars) is stored at the entry's
 // position, so a batch of U entries costs one round of independent index
 // loads and then one round of row loads; vertex boundaries are read off the
-// per-entry vertex ids, and the chunk's neighbours irow[cs - 1], irow[ce]
-// tell whether its first and last vertices are cut.
+// per-entry vertex ids, and the neighbours irow[p0 - 1], irow[p1] of a row
+// group's share [p0, p1) tell whether its first and last vertices are cut.
+#include <algorithm>
+
 #include "launch.hpp"
 
 namespace ccm {
@@ -66,14 +69,22 @@ __device__ __forceinline__ Meta load_meta(const DevGraph& g, int64_t p, const Pa
     return m;
 }
 
-// Chunk width of each row layout (the host's chunk_for(d) for the d the
+// Row-group share of each row layout (the host's chunk_for(d) for the d the
 // layout serves).
 template <int LPR, int NPER>
 constexpr int chunk_of() {
     return LPR * NPER <= 64 ? 16 : LPR * NPER <= 256 ? 32 : 64;
 }
 
-// Incidence data of a whole chunk, loaded once at chunk start and spread over
+// Slots of LPR entries whose incidence data a row group loads in one round:
+// its whole share unless the window is a hub's.
+template <int LPR, int NPER>
+constexpr int meta_slots() {
+    constexpr int c = chunk_of<LPR, NPER>() / LPR;
+    return c >= 1 ? c : 1;
+}
+
+// Incidence data of up to NM LPR entries, loaded in one round and spread over
 // the lanes of the row group (entry j LPR + lane in slot j); an entry's data
 // is then fetched with lane shuffles instead of another round of loads.
 template <int LPR, int NM>
@@ -144,19 +155,25 @@ __device__ __forceinline__ Meta chunk_meta_get(const ChunkMeta<LPR, NM>& cm, int
     return m;
 }
 
-struct ChunkCtx {
-    int64_t cs, ce;      // incidence range of the chunk
-    int64_t vprev;       // vertex of entry cs - 1 (-1 if none)
-    int64_t vnext;       // vertex of entry ce (-1 if none)
+// Share [p0, p1) of row group rg (of GPB) in window w, and the vertices of the
+// entries just before and after it inside the window (-1 if none).
+// (Entry positions fit 32 bits: the incidence offsets are 32-bit.)
+struct GroupRange {
+    int p0, p1;
+    int vprev, vnext;
 };
 
-__device__ __forceinline__ ChunkCtx chunk_ctx(const DevGraph& g, int64_t c) {
-    ChunkCtx x;
-    x.cs = c * g.chunk;
-    x.ce = x.cs + g.chunk < g.nent ? x.cs + g.chunk : g.nent;
-    x.vprev = x.cs > 0 ? g.irow[x.cs - 1] : -1;
-    x.vnext = x.ce < g.nent ? g.irow[x.ce] : -1;
-    return x;
+__device__ __forceinline__ GroupRange group_range(const DevGraph& g, int w, int rg, int gpb) {
+    const int2 wn = g.win[w];
+    const int ws = wn.x, we = wn.y;
+    const int sc = (we - ws + gpb - 1) / gpb;
+    GroupRange r;
+    r.p0 = ws + rg * sc < we ? ws + rg * sc : we;
+    r.p1 = r.p0 + sc < we ? r.p0 + sc : we;
+    const bool any = r.p0 < r.p1;
+    r.vprev = (any && r.p0 > ws) ? g.irow[r.p0 - 1] : -1;
+    r.vnext = (any && r.p1 < we) ? g.irow[r.p1] : -1;
+    return r;
 }
 
 template <int LPR, int NPER>
@@ -212,191 +229,160 @@ __device__ __forceinline__ void scatter_finish(int64_t v, int d, int gl, const S
 }
 
 template <int LPR, int NPER, int Q, bool DIAG>
-__global__ __launch_bounds__(kBlock) void k_scatter_chunk(DevGraph g, int d, ScatterOut so,
-                                                          const double* __restrict__ Z, Payload pl,
-                                                          double* __restrict__ partials) {
+__global__ __launch_bounds__(kBlock) void k_scatter_win(DevGraph g, int d, ScatterOut so,
+                                                        const double* __restrict__ Z, Payload pl,
+                                                        double* __restrict__ partials) {
     constexpr int U = Unroll<NPER>::US;
-    constexpr int NM = chunk_of<LPR, NPER>() / LPR > 0 ? chunk_of<LPR, NPER>() / LPR : 1;
-    constexpr bool PF = NM <= 4;  // chunk data fits a few registers per lane
-    const int gl = (threadIdx.x & 63) % LPR;
+    constexpr int NM = meta_slots<LPR, NPER>();
+    constexpr bool PF = NM <= 4;  // share data fits a few registers per lane
     constexpr int GPB = kBlock / LPR;
-    const int CW = 2 * d;
+    constexpr int NS = DIAG ? 2 : 1;
+    // later pieces of cut vertices: [row group][sum][value][lane]
+    __shared__ double piece[GPB][NS][NPER][LPR];
+    __shared__ int head_v[GPB];  // vertex of the row group's first piece if cut, else -1
+    const int gl = (threadIdx.x & 63) % LPR;
+    const int rg = threadIdx.x / LPR;
     double acc4[kScatterNV] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t c = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; c < g.nchunks;
-         c += int64_t(gridDim.x) * GPB) {
-        const ChunkCtx cx = chunk_ctx(g, c);
-        ChunkMeta<LPR, PF ? NM : 1> cm;
-        if constexpr (PF) chunk_meta_load<LPR, NM, Q, DIAG>(g, cx.cs, cx.ce, gl, pl, cm);
-        int64_t vcur = -1;
+    for (int w = blockIdx.x; w < int(g.nwin); w += gridDim.x) {
+        const GroupRange gr = group_range(g, w, rg, GPB);
+        int vcur = -1;
         bool first = true;
+        int head = -1;
         double acc[NPER], dg[NPER], xr[NPER], ar[NPER];
 #pragma unroll
         for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = xr[t] = ar[t] = 0.0;
-        auto flush = [&](bool cut) {
-            if (!cut) {
-                if constexpr (!Unroll<NPER>::PREFETCH) {
-                    double x2[NPER], a2[NPER];
-                    load_row<LPR, NPER>(so.X, vcur, d, gl, x2);
-                    load_row<LPR, NPER>(so.A, vcur, d, gl, a2);
-                    scatter_finish<LPR, NPER, DIAG>(vcur, d, gl, so, x2, a2, acc, dg, acc4);
-                } else {
-                    scatter_finish<LPR, NPER, DIAG>(vcur, d, gl, so, xr, ar, acc, dg, acc4);
-                }
+        auto finish = [&]() {
+            if constexpr (!Unroll<NPER>::PREFETCH) {
+                double x2[NPER], a2[NPER];
+                load_row<LPR, NPER>(so.X, vcur, d, gl, x2);
+                load_row<LPR, NPER>(so.A, vcur, d, gl, a2);
+                scatter_finish<LPR, NPER, DIAG>(vcur, d, gl, so, x2, a2, acc, dg, acc4);
             } else {
-                double* cr = g.carry + (c * 2 + (first ? 0 : 1)) * CW;
-#pragma unroll
-                for (int t = 0; t < NPER; ++t) {
-                    const int k = gl + LPR * t;
-                    if (k < d) {
-                        cr[k] = acc[t];
-                        if constexpr (DIAG) cr[d + k] = dg[t];
-                    }
-                }
+                scatter_finish<LPR, NPER, DIAG>(vcur, d, gl, so, xr, ar, acc, dg, acc4);
             }
         };
-        for (int64_t p0 = cx.cs; p0 < cx.ce; p0 += U) {
-            Meta mt[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (p0 + u < cx.ce) {
-                    if constexpr (PF)
-                        mt[u] = chunk_meta_get<LPR, NM, Q, DIAG, false>(cm, int(p0 + u - cx.cs));
-                    else
-                        mt[u] = load_meta<Q, DIAG>(g, p0 + u, pl);
-                }
-            double zr[U][NPER];
-            uint32_t lb[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool ok = p0 + u < cx.ce;
+        // vertex vcur has no more entries in this share
+        auto done = [&](bool cut_start) {
+            if (!cut_start) {
+                finish();
+            } else {
 #pragma unroll
                 for (int t = 0; t < NPER; ++t) {
-                    const int k = gl + LPR * t;
-                    zr[u][t] = (ok && k < d) ? Z[int64_t(mt[u].l) * d + k] : 0.0;
+                    piece[rg][0][t][gl] = acc[t];
+                    if constexpr (DIAG) piece[rg][NS - 1][t][gl] = dg[t];
                 }
-                lb[u] = 0u;
-                if constexpr (DIAG && Q != kQ2)
-                    if (ok) lb[u] = pl.lbits[int64_t(mt[u].l) * LPR + gl];
+                head = vcur;
             }
+        };
+        constexpr int CP = NM * LPR;  // entries per round of incidence loads
+        for (int pc = gr.p0, pe = 0; pc < gr.p1; pc = pe) {
+            pe = (PF && gr.p1 - pc > CP) ? pc + CP : gr.p1;
+            ChunkMeta<LPR, PF ? NM : 1> cm;
+            if constexpr (PF) chunk_meta_load<LPR, NM, Q, DIAG>(g, pc, pe, gl, pl, cm);
+            for (int p0 = pc; p0 < pe; p0 += U) {
+                Meta mt[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (p0 + u >= cx.ce) break;
-                const Meta& m = mt[u];
-                if (m.v != vcur) {
-                    if (vcur >= 0) {
-                        flush(first && vcur == cx.vprev);
-                        first = false;
+                for (int u = 0; u < U; ++u)
+                    if (p0 + u < pe) {
+                        if constexpr (PF)
+                            mt[u] = chunk_meta_get<LPR, NM, Q, DIAG, false>(cm, p0 + u - pc);
+                        else
+                            mt[u] = load_meta<Q, DIAG>(g, p0 + u, pl);
                     }
-                    vcur = m.v;
-                    if constexpr (Unroll<NPER>::PREFETCH) {
-                        load_row<LPR, NPER>(so.X, vcur, d, gl, xr);
-                        load_row<LPR, NPER>(so.A, vcur, d, gl, ar);
-                    }
+                double zr[U][NPER];
+                uint32_t lb[U];
 #pragma unroll
-                    for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = 0.0;
+                for (int u = 0; u < U; ++u) {
+                    const bool ok = p0 + u < pe;
+#pragma unroll
+                    for (int t = 0; t < NPER; ++t) {
+                        const int k = gl + LPR * t;
+                        zr[u][t] = (ok && k < d) ? Z[int64_t(mt[u].l) * d + k] : 0.0;
+                    }
+                    lb[u] = 0u;
+                    if constexpr (DIAG && Q != kQ2)
+                        if (ok) lb[u] = pl.lbits[int64_t(mt[u].l) * LPR + gl];
                 }
 #pragma unroll
-                for (int t = 0; t < NPER; ++t) acc[t] += m.pos ? zr[u][t] : -zr[u][t];
-                if constexpr (DIAG) {
-                    if constexpr (Q == kQ2) {
-                        if (m.a >= 1.0) {
-#pragma unroll
-                            for (int t = 0; t < NPER; ++t) dg[t] += 1.0;
-                        } else if (m.a > 0.0) {
-#pragma unroll
-                            for (int t = 0; t < NPER; ++t) {
-                                const double yh = zr[u][t] * m.ir;
-                                dg[t] += m.a * (1.0 - yh * yh);
-                            }
+                for (int u = 0; u < U; ++u) {
+                    if (p0 + u >= pe) break;
+                    const Meta& m = mt[u];
+                    if (m.v != vcur) {
+                        if (vcur >= 0) {
+                            done(first && vcur == gr.vprev);
+                            first = false;
                         }
-                    } else if constexpr (Q == kQ1) {
+                        vcur = m.v;
+                        if constexpr (Unroll<NPER>::PREFETCH) {
+                            load_row<LPR, NPER>(so.X, vcur, d, gl, xr);
+                            load_row<LPR, NPER>(so.A, vcur, d, gl, ar);
+                        }
 #pragma unroll
-                        for (int t = 0; t < NPER; ++t)
-                            if ((lb[u] >> t) & 1u) dg[t] += 1.0;
-                    } else {
-                        if (m.cnt < 0) {
+                        for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = 0.0;
+                    }
 #pragma unroll
-                            for (int t = 0; t < NPER; ++t) dg[t] += 1.0;
-                        } else if (m.cnt > 0) {
-                            const double f = 1.0 - 1.0 / double(m.cnt);
+                    for (int t = 0; t < NPER; ++t) acc[t] += m.pos ? zr[u][t] : -zr[u][t];
+                    if constexpr (DIAG) {
+                        if constexpr (Q == kQ2) {
+                            if (m.a >= 1.0) {
+#pragma unroll
+                                for (int t = 0; t < NPER; ++t) dg[t] += 1.0;
+                            } else if (m.a > 0.0) {
+#pragma unroll
+                                for (int t = 0; t < NPER; ++t) {
+                                    const double yh = zr[u][t] * m.ir;
+                                    dg[t] += m.a * (1.0 - yh * yh);
+                                }
+                            }
+                        } else if constexpr (Q == kQ1) {
 #pragma unroll
                             for (int t = 0; t < NPER; ++t)
-                                if ((lb[u] >> t) & 1u) dg[t] += f;
+                                if ((lb[u] >> t) & 1u) dg[t] += 1.0;
+                        } else {
+                            if (m.cnt < 0) {
+#pragma unroll
+                                for (int t = 0; t < NPER; ++t) dg[t] += 1.0;
+                            } else if (m.cnt > 0) {
+                                const double f = 1.0 - 1.0 / double(m.cnt);
+#pragma unroll
+                                for (int t = 0; t < NPER; ++t)
+                                    if ((lb[u] >> t) & 1u) dg[t] += f;
+                            }
                         }
                     }
                 }
             }
         }
-        if (vcur >= 0) flush((first && vcur == cx.vprev) || vcur == cx.vnext);
-    }
-    block_reduce_store<kScatterNV>(acc4, partials + blockIdx.x * kScatterNV);
-}
-
-// Sum, in chunk order, of the partial rows a cut vertex left in the carry
-// slots of chunks c0..c1 (slot 0 where the chunk starts inside the vertex's
-// range, else 1); the first three are loaded in one round.
-template <int LPR, int NPER, bool DIAG>
-__device__ __forceinline__ void sum_carries(const DevGraph& g, int d, int gl, int64_t vb,
-                                            int64_t ve, double (&acc)[NPER],
-                                            double (&dg)[NPER]) {
-#pragma unroll
-    for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = 0.0;
-    if (ve <= vb) return;
-    const int C = g.chunk;
-    const int CW = 2 * d;
-    const int64_t c0 = vb / C, c1 = (ve - 1) / C;
-    double p[3][NPER], q[3][NPER];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int64_t c = c0 + j;
-        const double* cr = g.carry + (c * 2 + (c * C >= vb ? 0 : 1)) * CW;
-#pragma unroll
-        for (int t = 0; t < NPER; ++t) {
-            const int k = gl + LPR * t;
-            const bool ok = c <= c1 && k < d;
-            p[j][t] = ok ? cr[k] : 0.0;
-            q[j][t] = (DIAG && ok) ? cr[d + k] : 0.0;
+        // the last vertex: finished here, or (continuing past the share)
+        // after the barrier with the later row groups' pieces
+        bool pend = false;
+        if (vcur >= 0) {
+            const bool cs = first && vcur == gr.vprev;
+            if (!cs && vcur == gr.vnext) pend = true;
+            else done(cs);
         }
-    }
+        if (gl == 0) head_v[rg] = head;
+        __syncthreads();
+        if (pend) {
+            for (int j = rg + 1; j < GPB && head_v[j] == vcur; ++j) {
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        if (c0 + j > c1) break;
-#pragma unroll
-        for (int t = 0; t < NPER; ++t) {
-            acc[t] += p[j][t];
-            if constexpr (DIAG) dg[t] += q[j][t];
-        }
-    }
-    for (int64_t c = c0 + 3; c <= c1; ++c) {
-        const double* cr = g.carry + (c * 2 + (c * C >= vb ? 0 : 1)) * CW;
-#pragma unroll
-        for (int t = 0; t < NPER; ++t) {
-            const int k = gl + LPR * t;
-            if (k < d) {
-                acc[t] += cr[k];
-                if constexpr (DIAG) dg[t] += cr[d + k];
+                for (int t = 0; t < NPER; ++t) {
+                    acc[t] += piece[j][0][t][gl];
+                    if constexpr (DIAG) dg[t] += piece[j][NS - 1][t][gl];
+                }
             }
+            finish();
         }
+        __syncthreads();
     }
-}
-
-// The fix-up kernels use a whole wave per vertex row (NPER = ceil(d / 64)):
-// they are latency-bound, and more waves in flight hide more of it.
-template <int NPER, bool DIAG>
-__global__ __launch_bounds__(kBlock) void k_scatter_fix(DevGraph g, int d, ScatterOut so,
-                                                        double* __restrict__ partials) {
-    constexpr int LPR = 64;
-    const int gl = threadIdx.x & 63;
-    constexpr int GPB = kBlock / LPR;
-    double acc4[kScatterNV] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t s = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; s < g.nspecial;
-         s += int64_t(gridDim.x) * GPB) {
-        const int4 sp = g.special[s];
-        const int64_t v = sp.x;
+    // isolated vertices
+    for (int64_t i = int64_t(blockIdx.x) * GPB + rg; i < g.niso; i += int64_t(gridDim.x) * GPB) {
+        const int64_t v = g.iso[i];
         double acc[NPER], dg[NPER], xr[NPER], ar[NPER];
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = 0.0;
         load_row<LPR, NPER>(so.X, v, d, gl, xr);
         load_row<LPR, NPER>(so.A, v, d, gl, ar);
-        sum_carries<LPR, NPER, DIAG>(g, d, gl, sp.y, sp.z, acc, dg);
         scatter_finish<LPR, NPER, DIAG>(v, d, gl, so, xr, ar, acc, dg, acc4);
     }
     block_reduce_store<kScatterNV>(acc4, partials + blockIdx.x * kScatterNV);
@@ -492,138 +478,146 @@ __device__ __forceinline__ void matvec_term(const Meta& m, const double (&dl)[NP
 }
 
 template <int LPR, int NPER, int Q, int MODE>
-__global__ __launch_bounds__(kBlock) void k_matvec_chunk(DevGraph g, int d,
-                                                         const double* __restrict__ V,
-                                                         const double* __restrict__ Pi,
-                                                         Payload pl, MatvecOut mo,
-                                                         double* __restrict__ partials,
-                                                         CgSkip skip) {
+__global__ __launch_bounds__(kBlock) void k_matvec_win(DevGraph g, int d,
+                                                       const double* __restrict__ V,
+                                                       const double* __restrict__ Pi,
+                                                       Payload pl, MatvecOut mo,
+                                                       double* __restrict__ partials,
+                                                       CgSkip skip) {
     if (cg_skip(skip)) return;
     constexpr int U = Unroll<NPER>::U;
     constexpr bool PAY = MODE != 1;
     constexpr int QP = MODE == 2 ? kQ2 : Q;
-    constexpr int NM = chunk_of<LPR, NPER>() / LPR > 0 ? chunk_of<LPR, NPER>() / LPR : 1;
-    constexpr bool PF = NM <= 4;  // chunk data fits a few registers per lane
-    const int gl = (threadIdx.x & 63) % LPR;
+    constexpr int NM = meta_slots<LPR, NPER>();
+    constexpr bool PF = NM <= 4;  // share data fits a few registers per lane
     constexpr int GPB = kBlock / LPR;
-    const int CW = 2 * d;
+    // later pieces of cut vertices: [row group][value][lane]
+    __shared__ double piece[GPB][NPER][LPR];
+    __shared__ int head_v[GPB];  // vertex of the row group's first piece if cut, else -1
+    const int gl = (threadIdx.x & 63) % LPR;
+    const int rg = threadIdx.x / LPR;
     double dot = 0.0;
-    for (int64_t c = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; c < g.nchunks;
-         c += int64_t(gridDim.x) * GPB) {
-        const ChunkCtx cx = chunk_ctx(g, c);
-        ChunkMeta<LPR, PF ? NM : 1> cm;
-        if constexpr (PF) chunk_meta_load<LPR, NM, QP, PAY>(g, cx.cs, cx.ce, gl, pl, cm);
-        int64_t vcur = -1;
+    for (int w = blockIdx.x; w < int(g.nwin); w += gridDim.x) {
+        const GroupRange gr = group_range(g, w, rg, GPB);
+        int vcur = -1;
         bool first = true;
+        int head = -1;
         double vi[NPER], acc[NPER];
 #pragma unroll
         for (int t = 0; t < NPER; ++t) vi[t] = acc[t] = 0.0;
-        auto flush = [&](bool cut) {
-            if (!cut) {
+        // vertex vcur has no more entries in this share
+        auto done = [&](bool cut_start) {
+            if (!cut_start) {
                 matvec_finish<LPR, NPER>(vcur, d, gl, mo, vi, acc, dot);
             } else {
-                double* cr = g.carry + (c * 2 + (first ? 0 : 1)) * CW;
 #pragma unroll
-                for (int t = 0; t < NPER; ++t) {
-                    const int k = gl + LPR * t;
-                    if (k < d) cr[k] = acc[t];
-                }
+                for (int t = 0; t < NPER; ++t) piece[rg][t][gl] = acc[t];
+                head = vcur;
             }
         };
-        for (int64_t p0 = cx.cs; p0 < cx.ce; p0 += U) {
-            Meta mt[U];
+        constexpr int CP = NM * LPR;  // entries per round of incidence loads
+        for (int pc = gr.p0, pe = 0; pc < gr.p1; pc = pe) {
+            pe = (PF && gr.p1 - pc > CP) ? pc + CP : gr.p1;
+            ChunkMeta<LPR, PF ? NM : 1> cm;
+            if constexpr (PF) chunk_meta_load<LPR, NM, QP, PAY>(g, pc, pe, gl, pl, cm);
+            for (int p0 = pc; p0 < pe; p0 += U) {
+                Meta mt[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (p0 + u < cx.ce) {
-                    if constexpr (PF)
-                        mt[u] = chunk_meta_get<LPR, NM, QP, PAY, MODE == 2>(cm, int(p0 + u - cx.cs));
-                    else
-                        mt[u] = load_meta<QP, PAY, MODE == 2>(g, p0 + u, pl);
+                for (int u = 0; u < U; ++u)
+                    if (p0 + u < pe) {
+                        if constexpr (PF)
+                            mt[u] = chunk_meta_get<LPR, NM, QP, PAY, MODE == 2>(cm, p0 + u - pc);
+                        else
+                            mt[u] = load_meta<QP, PAY, MODE == 2>(g, p0 + u, pl);
+                    }
+                // the first vertex starting in this batch has its row gathered
+                // with the batch; any further one is loaded when reached
+                int un = -1;
+                int64_t vnew = -1;
+                double vn[NPER];
+                if constexpr (Unroll<NPER>::PREFETCH) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (un < 0 && p0 + u < pe &&
+                            mt[u].v != (u == 0 ? vcur : int64_t(mt[u > 0 ? u - 1 : 0].v))) {
+                            un = u;
+                            vnew = mt[u].v;
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < NPER; ++t) {
+                        const int k = gl + LPR * t;
+                        vn[t] = (vnew >= 0 && k < d) ? V[vnew * d + k] : 0.0;
+                    }
                 }
-            // the first vertex starting in this batch has its row gathered
-            // with the batch; any further one is loaded when reached
-            int un = -1;
-            int64_t vnew = -1;
-            double vn[NPER];
-            if constexpr (Unroll<NPER>::PREFETCH) {
+                double vo[U][NPER], pv[U][NPER];
+                uint32_t lb[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    if (un < 0 && p0 + u < cx.ce &&
-                        mt[u].v != (u == 0 ? vcur : int64_t(mt[u > 0 ? u - 1 : 0].v))) {
-                        un = u;
-                        vnew = mt[u].v;
+                    const bool ok = p0 + u < pe;
+                    const bool rows = ok && PAY && QP == kQ2 && mt[u].f != 0.0;
+#pragma unroll
+                    for (int t = 0; t < NPER; ++t) {
+                        const int k = gl + LPR * t;
+                        vo[u][t] = (ok && k < d) ? V[int64_t(mt[u].o) * d + k] : 0.0;
+                        pv[u][t] = (rows && k < d) ? Pi[int64_t(mt[u].l) * d + k] : 0.0;
                     }
+                    lb[u] = 0u;
+                    if constexpr (PAY && QP != kQ2)
+                        if (ok) lb[u] = pl.lbits[int64_t(mt[u].l) * LPR + gl];
                 }
 #pragma unroll
-                for (int t = 0; t < NPER; ++t) {
-                    const int k = gl + LPR * t;
-                    vn[t] = (vnew >= 0 && k < d) ? V[vnew * d + k] : 0.0;
-                }
-            }
-            double vo[U][NPER], pv[U][NPER];
-            uint32_t lb[U];
+                for (int u = 0; u < U; ++u) {
+                    if (p0 + u >= pe) break;
+                    const Meta& m = mt[u];
+                    if (m.v != vcur) {
+                        if (vcur >= 0) {
+                            done(first && vcur == gr.vprev);
+                            first = false;
+                        }
+                        vcur = m.v;
+                        if (u == un) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool ok = p0 + u < cx.ce;
-                const bool rows = ok && PAY && QP == kQ2 && mt[u].f != 0.0;
+                            for (int t = 0; t < NPER; ++t) vi[t] = vn[t];
+                        } else {
+                            load_row<LPR, NPER>(V, vcur, d, gl, vi);
+                        }
 #pragma unroll
-                for (int t = 0; t < NPER; ++t) {
-                    const int k = gl + LPR * t;
-                    vo[u][t] = (ok && k < d) ? V[int64_t(mt[u].o) * d + k] : 0.0;
-                    pv[u][t] = (rows && k < d) ? Pi[int64_t(mt[u].l) * d + k] : 0.0;
-                }
-                lb[u] = 0u;
-                if constexpr (PAY && QP != kQ2)
-                    if (ok) lb[u] = pl.lbits[int64_t(mt[u].l) * LPR + gl];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (p0 + u >= cx.ce) break;
-                const Meta& m = mt[u];
-                if (m.v != vcur) {
-                    if (vcur >= 0) {
-                        flush(first && vcur == cx.vprev);
-                        first = false;
+                        for (int t = 0; t < NPER; ++t) acc[t] = 0.0;
                     }
-                    vcur = m.v;
-                    if (u == un) {
+                    double dl[NPER];
 #pragma unroll
-                        for (int t = 0; t < NPER; ++t) vi[t] = vn[t];
-                    } else {
-                        load_row<LPR, NPER>(V, vcur, d, gl, vi);
-                    }
-#pragma unroll
-                    for (int t = 0; t < NPER; ++t) acc[t] = 0.0;
+                    for (int t = 0; t < NPER; ++t) dl[t] = vi[t] - vo[u][t];
+                    matvec_term<LPR, NPER, Q, MODE>(m, dl, pv[u], lb[u], acc);
                 }
-                double dl[NPER];
-#pragma unroll
-                for (int t = 0; t < NPER; ++t) dl[t] = vi[t] - vo[u][t];
-                matvec_term<LPR, NPER, Q, MODE>(m, dl, pv[u], lb[u], acc);
             }
         }
-        if (vcur >= 0) flush((first && vcur == cx.vprev) || vcur == cx.vnext);
+        // the last vertex: finished here, or (continuing past the share)
+        // after the barrier with the later row groups' pieces
+        bool pend = false;
+        if (vcur >= 0) {
+            const bool cs = first && vcur == gr.vprev;
+            if (!cs && vcur == gr.vnext) pend = true;
+            else done(cs);
+        }
+        if (gl == 0) head_v[rg] = head;
+        __syncthreads();
+        if (pend) {
+            for (int j = rg + 1; j < GPB && head_v[j] == vcur; ++j) {
+#pragma unroll
+                for (int t = 0; t < NPER; ++t) acc[t] += piece[j][t][gl];
+            }
+            matvec_finish<LPR, NPER>(vcur, d, gl, mo, vi, acc, dot);
+        }
+        __syncthreads();
     }
-    double dt[1] = {dot};
-    block_reduce_store<kMatvecNV>(dt, partials + blockIdx.x * kMatvecNV);
-}
-
-template <int NPER>
-__global__ __launch_bounds__(kBlock) void k_matvec_fix(DevGraph g, int d,
-                                                       const double* __restrict__ V, MatvecOut mo,
-                                                       double* __restrict__ partials,
-                                                       CgSkip skip) {
-    if (cg_skip(skip)) return;
-    constexpr int LPR = 64;
-    const int gl = threadIdx.x & 63;
-    constexpr int GPB = kBlock / LPR;
-    double dot = 0.0;
-    for (int64_t s = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; s < g.nspecial;
-         s += int64_t(gridDim.x) * GPB) {
-        const int4 sp = g.special[s];
-        const int64_t v = sp.x;
-        double vi[NPER], acc[NPER], unused[NPER];
+    // isolated vertices
+    for (int64_t i = int64_t(blockIdx.x) * GPB + rg; i < g.niso; i += int64_t(gridDim.x) * GPB) {
+        const int64_t v = g.iso[i];
+        double vi[NPER], acc[NPER];
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) acc[t] = 0.0;
         load_row<LPR, NPER>(V, v, d, gl, vi);
-        sum_carries<LPR, NPER, false>(g, d, gl, sp.y, sp.z, acc, unused);
         matvec_finish<LPR, NPER>(v, d, gl, mo, vi, acc, dot);
     }
     double dt[1] = {dot};
@@ -631,6 +625,14 @@ __global__ __launch_bounds__(kBlock) void k_matvec_fix(DevGraph g, int d,
 }
 
 }  // namespace
+
+// one workgroup per window, enough to give every isolated vertex a row group
+template <int LPR>
+static int window_grid(const DevGraph& g) {
+    const int64_t gpb = kBlock / LPR;
+    int64_t b = std::max<int64_t>(g.nwin, (g.niso + gpb - 1) / gpb);
+    return int(std::min<int64_t>(std::max<int64_t>(b, 1), kMaxGrid));
+}
 
 int launch_scatter(const DevGraph& g, int d, int qk, double cx, const double* X, double ca,
                    const double* A, double cz, const double* Z, double* out, bool diag, Payload pl,
@@ -641,32 +643,18 @@ int launch_scatter(const DevGraph& g, int d, int qk, double cx, const double* X,
     ScatterOut so{cx, ca, cz, sigma, X, A, out, Dinv, rowstats};
     dispatch_row(d, [&](auto L, auto N) {
         constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
-        const int g1 = g.nchunks > 0 ? row_grid(g.nchunks, lpr) : 0;
-        const int g2 = row_grid(g.nspecial, 64);
+        const int g1 = window_grid<lpr>(g);
         if (!diag) {
-            if (g1 > 0)
-                hipLaunchKernelGGL((k_scatter_chunk<lpr, nper, kQ2, false>), dim3(g1), dim3(kBlock),
-                                   0, s, g, d, so, Z, pl, partials);
-            dispatch_fix(d, [&](auto F) {
-                constexpr int nf = decltype(F)::value;
-                hipLaunchKernelGGL((k_scatter_fix<nf, false>), dim3(g2), dim3(kBlock), 0, s, g, d,
-                                   so, partials + g1 * kScatterNV);
-            });
+            hipLaunchKernelGGL((k_scatter_win<lpr, nper, kQ2, false>), dim3(g1), dim3(kBlock), 0,
+                               s, g, d, so, Z, pl, partials);
         } else {
-            if (g1 > 0) {
-                dispatch_q(qk, [&](auto Qc) {
-                    constexpr int q = decltype(Qc)::value;
-                    hipLaunchKernelGGL((k_scatter_chunk<lpr, nper, q, true>), dim3(g1),
-                                       dim3(kBlock), 0, s, g, d, so, Z, pl, partials);
-                });
-            }
-            dispatch_fix(d, [&](auto F) {
-                constexpr int nf = decltype(F)::value;
-                hipLaunchKernelGGL((k_scatter_fix<nf, true>), dim3(g2), dim3(kBlock), 0, s, g, d,
-                                   so, partials + g1 * kScatterNV);
+            dispatch_q(qk, [&](auto Qc) {
+                constexpr int q = decltype(Qc)::value;
+                hipLaunchKernelGGL((k_scatter_win<lpr, nper, q, true>), dim3(g1), dim3(kBlock), 0,
+                                   s, g, d, so, Z, pl, partials);
             });
         }
-        total = g1 + g2;
+        total = g1;
     });
     return total;
 }
@@ -679,29 +667,21 @@ int launch_matvec(const DevGraph& g, int d, int qk, int mode, const double* V, c
     MatvecOut mo{sigma, c0, dscale, out};
     dispatch_row(d, [&](auto L, auto N) {
         constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
-        const int g1 = g.nchunks > 0 ? row_grid(g.nchunks, lpr) : 0;
-        const int g2 = row_grid(g.nspecial, 64);
-        if (g1 > 0) {
-            if (mode == 1) {
-                hipLaunchKernelGGL((k_matvec_chunk<lpr, nper, kQ2, 1>), dim3(g1), dim3(kBlock), 0,
-                                   s, g, d, V, Pi, pl, mo, partials, skip);
-            } else if (mode == 2) {
-                hipLaunchKernelGGL((k_matvec_chunk<lpr, nper, kQ2, 2>), dim3(g1), dim3(kBlock), 0,
-                                   s, g, d, V, Pi, pl, mo, partials, skip);
-            } else {
-                dispatch_q(qk, [&](auto Qc) {
-                    constexpr int q = decltype(Qc)::value;
-                    hipLaunchKernelGGL((k_matvec_chunk<lpr, nper, q, 0>), dim3(g1), dim3(kBlock),
-                                       0, s, g, d, V, Pi, pl, mo, partials, skip);
-                });
-            }
+        const int g1 = window_grid<lpr>(g);
+        if (mode == 1) {
+            hipLaunchKernelGGL((k_matvec_win<lpr, nper, kQ2, 1>), dim3(g1), dim3(kBlock), 0, s, g,
+                               d, V, Pi, pl, mo, partials, skip);
+        } else if (mode == 2) {
+            hipLaunchKernelGGL((k_matvec_win<lpr, nper, kQ2, 2>), dim3(g1), dim3(kBlock), 0, s, g,
+                               d, V, Pi, pl, mo, partials, skip);
+        } else {
+            dispatch_q(qk, [&](auto Qc) {
+                constexpr int q = decltype(Qc)::value;
+                hipLaunchKernelGGL((k_matvec_win<lpr, nper, q, 0>), dim3(g1), dim3(kBlock), 0, s,
+                                   g, d, V, Pi, pl, mo, partials, skip);
+            });
         }
-        dispatch_fix(d, [&](auto F) {
-            constexpr int nf = decltype(F)::value;
-            hipLaunchKernelGGL((k_matvec_fix<nf>), dim3(g2), dim3(kBlock), 0, s, g, d, V, mo,
-                               partials + g1 * kMatvecNV, skip);
-        });
-        total = g1 + g2;
+        total = g1;
     });
     return total;
 }
