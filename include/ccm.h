@@ -14,8 +14,10 @@
  *    unless the name ends in _host.  Dense matrices are row-major FP64:
  *    A and X are n x d (row i = point i), U is m x d (row l = edge l).
  *  - The caller owns every buffer; the library never frees caller memory.
- *    Work space is allocated on the given stream (stream-ordered) and
- *    released before the call returns.  All work is enqueued on `stream`;
+ *    Work space is allocated on the given stream (stream-ordered) from a
+ *    memory pool the library keeps on each device, and handed back to that
+ *    pool before the call returns; the pool keeps it reserved for later
+ *    calls until ccm_release_workspace().  All work is enqueued on `stream`;
  *    calls that return host values synchronise that stream.
  *  - Edges: l = (src_l, dst_l) is an undirected edge with weight w_l.  On
  *    input any order and orientation is accepted; self-loops and zero
@@ -62,6 +64,11 @@ enum { CCM_CONVERGED = 0, CCM_MAX_ITER = 1, CCM_TIMEOUT = 2,
 const char* ccm_status_string(ccm_status s);
 const char* ccm_last_error(void);
 const char* ccm_version(void);
+
+/* Returns to the driver the device memory that the library's pools hold in
+ * reserve (work space freed by earlier calls, on every device used so far).
+ * Memory of work still in flight is kept.  CCM_E_HIP if a pool call fails. */
+ccm_status ccm_release_workspace(void);
 
 /* ---------------------------------------------------------------------------
  * Options.  Pass NULL for the defaults below, or fill a struct obtained from

@@ -22,7 +22,7 @@ __all__ = [
     "ccm_canonical_edge_count", "ccm_op_gather", "ccm_op_project", "ccm_op_prox",
     "ccm_op_scatter", "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy",
     "ccm_path_vjp", "CCMSolve", "ccm_solve_path_batched", "CcmInstance", "EXPORTED_SYMBOLS",
-    "ccm_build_knn_graph_u8",
+    "ccm_build_knn_graph_u8", "ccm_release_workspace",
 ]
 
 CCM_SSNAL, CCM_ADMM, CCM_AMA = 0, 1, 2
@@ -37,7 +37,7 @@ EXPORTED_SYMBOLS = [
     "ccm_build_knn_graph", "ccm_solve_path", "ccm_canonical_edge_count",
     "ccm_op_gather", "ccm_op_project", "ccm_op_prox", "ccm_op_scatter",
     "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy", "ccm_path_vjp",
-    "ccm_solve_path_batched", "ccm_build_knn_graph_u8",
+    "ccm_solve_path_batched", "ccm_build_knn_graph_u8", "ccm_release_workspace",
 ]
 
 
@@ -121,6 +121,7 @@ def lib():
         "ccm_path_vjp": [P, I64, I64, P, P, P, I64, F64, F64, P, P, P, P, P, P, F64, I32, P, P],
         "ccm_solve_path_batched": [P, I32, P, P, P, P, P, I32, F64, P, P, P, P, P, P, P],
         "ccm_build_knn_graph_u8": [P, I64, I64, F64, I32, F64, P, P, P, I64, P, P, P],
+        "ccm_release_workspace": [],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -175,6 +176,11 @@ def _i32(t):
 
 def ccm_version():
     return lib().ccm_version().decode()
+
+
+def ccm_release_workspace():
+    """Return the device memory the library keeps in reserve to the driver."""
+    _check(lib().ccm_release_workspace())
 
 
 def ccm_default_options(**kw):

@@ -45,32 +45,18 @@ ccm_status check_dims(int64_t n, int64_t d) {
     return CCM_OK;
 }
 
-// finite-ness of a device array, through a host copy in chunks
+// finite-ness of a device array: a flag set by a device pass over it
 ccm_status check_finite(const double* p, int64_t count, hipStream_t s, const char* what) {
     if (count <= 0) return CCM_OK;
-    // a device-side reduction would avoid the copy; the check runs once per call
-    const int64_t chunk = int64_t(1) << 22;
-    std::string buf;
-    double* h = nullptr;
-    if (hipHostMalloc((void**)&h, size_t(std::min(count, chunk)) * 8, hipHostMallocDefault) !=
-        hipSuccess)
-        return fail(CCM_E_NOMEM, "pinned buffer");
-    ccm_status st = CCM_OK;
-    for (int64_t o = 0; o < count && st == CCM_OK; o += chunk) {
-        const int64_t c = std::min(chunk, count - o);
-        if (hipMemcpyAsync(h, p + o, size_t(c) * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            st = fail(CCM_E_HIP, "copy for finiteness check failed");
-            break;
-        }
-        for (int64_t k = 0; k < c; ++k)
-            if (!std::isfinite(h[k])) {
-                st = fail(CCM_E_INVALID, std::string(what) + " contains NaN or Inf");
-                break;
-            }
-    }
-    (void)hipHostFree(h);
-    return st;
+    DevMem flag;
+    HIPCHK_API(flag.alloc(4, s));
+    HIPCHK_API(hipMemsetAsync(flag.p, 0, 4, s));
+    launch_flag_nonfinite(p, count, flag.as<int>(), s);
+    int h = 0;
+    HIPCHK_API(hipMemcpyAsync(&h, flag.p, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK_API(hipStreamSynchronize(s));
+    if (h) return fail(CCM_E_INVALID, std::string(what) + " contains NaN or Inf");
+    return CCM_OK;
 }
 
 ccm_options defaults() {
@@ -110,6 +96,12 @@ const char* ccm_status_string(ccm_status s) {
 const char* ccm_last_error(void) { return g_err.c_str(); }
 
 const char* ccm_version(void) { return "libccm 0.1 gfx950"; }
+
+ccm_status ccm_release_workspace(void) {
+    g_err.clear();
+    HIPCHK_API(release_workspace());
+    return CCM_OK;
+}
 
 ccm_options ccm_default_options(void) { return defaults(); }
 

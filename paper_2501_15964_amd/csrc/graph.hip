@@ -2,6 +2,8 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "graph.hpp"
@@ -108,6 +110,60 @@ __global__ __launch_bounds__(kBlock) void k_epos(int64_t cnt, const Inc* __restr
         else epos[2 * int64_t(~e) + 1] = int(p);
     }
 }
+
+}  // namespace
+
+namespace {
+constexpr int kMaxDev = 64;
+struct PoolTable {
+    std::mutex mu;
+    hipMemPool_t pools[kMaxDev] = {};
+    bool tried[kMaxDev] = {};
+};
+PoolTable& pool_table() {
+    static PoolTable t;
+    return t;
+}
+}  // namespace
+
+hipMemPool_t workspace_pool() {
+    PoolTable& t = pool_table();
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return nullptr;
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (!t.tried[dev]) {
+        t.tried[dev] = true;
+        hipMemPoolProps pr;
+        std::memset(&pr, 0, sizeof(pr));
+        pr.allocType = hipMemAllocationTypePinned;
+        pr.handleTypes = hipMemHandleTypeNone;
+        pr.location.type = hipMemLocationTypeDevice;
+        pr.location.id = dev;
+        hipMemPool_t p = nullptr;
+        if (hipMemPoolCreate(&p, &pr) == hipSuccess) {
+            uint64_t keep = UINT64_MAX;
+            if (hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess)
+                t.pools[dev] = p;
+            else
+                (void)hipMemPoolDestroy(p);
+        }
+    }
+    return t.pools[dev];
+}
+
+hipError_t release_workspace() {
+    PoolTable& t = pool_table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    hipError_t r = hipSuccess;
+    for (int dv = 0; dv < kMaxDev; ++dv) {
+        if (!t.pools[dv]) continue;
+        const hipError_t e = hipMemPoolTrimTo(t.pools[dv], 0);
+        if (e != hipSuccess) r = e;
+    }
+    return r;
+}
+
+namespace {
 
 int bits_for(int64_t n) {
     int b = 1;

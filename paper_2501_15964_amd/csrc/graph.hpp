@@ -8,6 +8,14 @@
 
 namespace ccm {
 
+// The library's memory pool on the current device (created on first use):
+// stream-ordered workspace comes from it, and what one call frees stays
+// reserved for the next instead of going back to the driver at every
+// synchronisation.  nullptr if the device offers no pools.
+hipMemPool_t workspace_pool();
+// Returns the unused reserve of every pool created so far to the driver.
+hipError_t release_workspace();
+
 // Stream-ordered device allocation that is released when the object dies.
 struct DevMem {
     void* p = nullptr;
@@ -24,7 +32,8 @@ struct DevMem {
         release();
         s = st;
         if (bytes == 0) bytes = 8;
-        return hipMallocAsync(&p, bytes, st);
+        hipMemPool_t pool = workspace_pool();
+        return pool ? hipMallocFromPoolAsync(&p, bytes, pool, st) : hipMallocAsync(&p, bytes, st);
     }
     template <class T>
     T* as() const { return static_cast<T*>(p); }

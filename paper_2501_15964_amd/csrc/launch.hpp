@@ -203,7 +203,20 @@ int launch_trial(int64_t N, const double* X, const double* D, double alpha, cons
                  const double* G, double* Xt, double* partials, hipStream_t s);
 // sum partials[p * nv + c] over p for every c < nv (1 <= nv <= 7); out[c] = total.
 void launch_finalize(const double* partials, int nparts, int nv, double* out, hipStream_t s);
+// several such sums in one launch (one workgroup each, same arithmetic)
+struct FinalizeJob {
+    const double* partials;
+    int nparts, nv;
+    double* out;
+};
+constexpr int kMaxFinalizeJobs = 8;
+struct FinalizeJobs {
+    FinalizeJob j[kMaxFinalizeJobs];
+};
+void launch_finalize_multi(const FinalizeJobs& jobs, int njobs, hipStream_t s);
 void launch_fill(double* x, int64_t N, double v, hipStream_t s);
+// flag[0] = 1 if some x[k] (k < count) is NaN or infinite; flag[0] is not cleared
+void launch_flag_nonfinite(const double* x, int64_t count, int* flag, hipStream_t s);
 // x += alpha y
 void launch_axpy(double* x, double alpha, const double* y, int64_t N, hipStream_t s);
 // out = a x + b y

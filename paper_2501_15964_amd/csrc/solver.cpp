@@ -183,9 +183,11 @@ struct Solver::Impl {
     DevMem fused, parent, rank, ltemp;
     size_t ltemp_bytes = 0;
     // reductions
-    DevMem pe, pet, ps, pst, pt, pk, pm, pm2, pupd0, pupd1, pwu0, pwu1, dsc, cgstate, cgflag,
+    DevMem pe, pet, ps, pst, pt, pk, pm, pm2, pupd0, pupd1, pwu0, pwu1, cgstate, cgflag,
         spread_work;
-    double* hs = nullptr;
+    double* hs = nullptr;          // scalar slots (host view)
+    double* dslot = nullptr;       // the same slots as the kernels address them
+    hipEvent_t sync_ev = nullptr;  // progress marker of the solver's stream
     int* hflag = nullptr;          // [0..1] status, [4..5] second pending chunk
     hipEvent_t cg_ev[2] = {nullptr, nullptr};
     CgBufs cg{};
@@ -220,6 +222,7 @@ struct Solver::Impl {
         if (hflag) (void)hipHostFree(hflag);
         for (auto e : cg_ev)
             if (e) (void)hipEventDestroy(e);
+        if (sync_ev) (void)hipEventDestroy(sync_ev);
     }
 
     ccm_status alloc() {
@@ -257,14 +260,17 @@ struct Solver::Impl {
         const size_t pb = size_t(kPartialsCap) * 8;
         for (DevMem* b : {&pe, &pet, &ps, &pst, &pt, &pk, &pm, &pm2, &pupd0, &pupd1, &pwu0, &pwu1})
             HIPCHK(b->alloc(pb, s));
-        HIPCHK(dsc.alloc(kNS * 8, s));
         HIPCHK(cgstate.alloc(8 * 8, s));
         HIPCHK(cgflag.alloc(4 * 4, s));
         HIPCHK(spread_work.alloc(size_t(spread_work_size(n, d)) * 8, s));
-        HIPCHK(hipHostMalloc((void**)&hs, kNS * 8, hipHostMallocDefault));
+        // scalar slots: coherent pinned host memory that the reduction kernels
+        // write directly, so a read needs no copy, only the stream's progress
+        HIPCHK(hipHostMalloc((void**)&hs, kNS * 8, hipHostMallocCoherent | hipHostMallocMapped));
+        std::memset(hs, 0, kNS * 8);
+        HIPCHK(hipHostGetDevicePointer((void**)&dslot, hs, 0));
         HIPCHK(hipHostMalloc((void**)&hflag, 8 * 4, hipHostMallocDefault));
         for (auto& e : cg_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        std::memset(hs, 0, kNS * 8);
+        HIPCHK(hipEventCreateWithFlags(&sync_ev, hipEventDisableTiming));
         X = bX.as<double>();
         Xt = bXt.as<double>();
         G = bG.as<double>();
@@ -292,15 +298,49 @@ struct Solver::Impl {
         return CCM_OK;
     }
 
-    // copy scalar slots [a, b) to the host and wait
-    ccm_status read(int a, int b) {
-        HIPCHK(hipMemcpyAsync(hs + a, dsc.as<double>() + a, size_t(b - a) * 8,
-                              hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        prof.harvest();
+    // Wait until event e has passed by polling it: a blocking wait sleeps and
+    // wakes up tens of microseconds after the device is done.
+    ccm_status spin(hipEvent_t e) {
+        hipError_t r;
+        while ((r = hipEventQuery(e)) == hipErrorNotReady) {
+        }
+        HIPCHK(r);
         return CCM_OK;
     }
-    double* slot(int k) { return dsc.as<double>() + k; }
+    // wait for the scalar slots written so far (the range [a, b) documents
+    // what the caller reads) and accumulate the profiling events recorded so
+    // far, unless harvest is false
+    ccm_status read(int a, int b, bool harvest = true) {
+        (void)a;
+        (void)b;
+        flush_finalize();
+        HIPCHK(hipEventRecord(sync_ev, s));
+        CHK(spin(sync_ev));
+        if (harvest) prof.harvest();
+        return CCM_OK;
+    }
+    double* slot(int k) { return dslot + k; }
+
+    // Reductions of per-block partials into scalar slots are deferred to the
+    // next read, which runs all of them in one launch.  A partials buffer with
+    // a pending reduction is not rewritten before that read except by another
+    // producer for the same slots (whose reduction then replaces it).
+    FinalizeJobs fin{};
+    int nfin = 0;
+    void defer_finalize(const double* part, int count, int nv, double* out, hipStream_t) {
+        for (int i = 0; i < nfin; ++i) {
+            if (fin.j[i].out == out) {
+                fin.j[i] = FinalizeJob{part, count, nv, out};
+                return;
+            }
+        }
+        if (nfin == kMaxFinalizeJobs) flush_finalize();
+        fin.j[nfin++] = FinalizeJob{part, count, nv, out};
+    }
+    void flush_finalize() {
+        launch_finalize_multi(fin, nfin, s);
+        nfin = 0;
+    }
 
     bool out_of_time() const {
         if (!(o.time_budget_s > 0)) return false;
@@ -314,7 +354,7 @@ struct Solver::Impl {
         // ||A||^2 and the data spread S (label threshold)
         {
             const int gp = launch_dot(A, A, N, pm.as<double>(), s);
-            launch_finalize(pm.as<double>(), gp, 1, slot(kNA), s);
+            defer_finalize(pm.as<double>(), gp, 1, slot(kNA), s);
             launch_spread(A, n, d, spread_work.as<double>(), slot(kSP), s);
             CHK(read(kNA, kSP + 1));
             nA = std::sqrt(hs[kNA]);
@@ -337,14 +377,14 @@ struct Solver::Impl {
                    int slot_out) {
         Timed t(prof, CCM_K_EDGE);
         const int gp = launch_edge_ssnal(g, d, qk, gamma, sigma, Xc, U, Pic, p, part, s);
-        launch_finalize(part, gp, kEdgeSsnalNV, slot(slot_out), s);
+        defer_finalize(part, gp, kEdgeSsnalNV, slot(slot_out), s);
     }
     void scatter_grad(const double* Xc, const double* Pic, Payload p, double gamma, double* Gc,
                       double* Dc, double* part, int slot_out) {
         Timed t(prof, CCM_K_SCATTER);
         const int gp = launch_scatter(g, d, qk, 1.0, Xc, -1.0, A, 1.0, Pic, Gc, true, p, gamma, sigma,
                                       Dc, part, s);
-        launch_finalize(part, gp, kScatterNV, slot(slot_out), s);
+        defer_finalize(part, gp, kScatterNV, slot(slot_out), s);
     }
     Ev make_ev(int e, int sc) const {
         Ev v;
@@ -381,104 +421,134 @@ struct Solver::Impl {
         return b;
     }
 
+    // ---- Jacobi-preconditioned CG ------------------------------------------------
     // Solve M x = b (M = I + sigma B^T P B for mode 0, I + sigma B^T B for
-    // mode 1) by Jacobi-preconditioned CG from x = 0; result in cg.x.
-    ccm_status cg_solve(int mode, const double* b, bool neg, const double* Dv, double thr,
-                        double gamma, const double* Pic, Payload p, int& iters) {
+    // mode 1) from x = 0; result in cg.x.  Iterations are enqueued in chunks;
+    // each launch issued after convergence returns at once (device-side flag)
+    // and is timed as "other".  The host waits for chunk k's status only after
+    // chunk k + 1 is enqueued, so its decision overlaps device work.  The first
+    // chunk is sized from the previous solve's iteration count (consecutive
+    // Newton systems need similar counts), later ones are half a chunk.
+    struct CgPending {
+        int j0 = 0, j1 = 0;
+        int64_t pid_end = 0;
+        std::vector<int64_t> upd, mv;
+        int* hf = nullptr;
+        hipEvent_t e = nullptr;
+    };
+    struct CgRun {
+        int mode = 0;
+        const double* Dv = nullptr;
+        double thr = 0, gamma = 0;
+        const double* Pic = nullptr;
+        Payload p{};
+        double mv_bytes = 0;
+        int j = 0;  // iterations enqueued
+        CgPending P[2];
+    } cr;
+
+    int cg_first(int mode) const {
+        const int chunk = std::max(1, o.cg_chunk);
+        return std::max(2, std::min(2 * chunk, cg_pred[mode & 1]));
+    }
+    int cg_later() const { return std::max(2, std::max(1, o.cg_chunk) / 2); }
+
+    // x = 0, r = b (negated if neg), the preconditioned residual and its matvec
+    void cg_begin(int mode, const double* b, bool neg, const double* Dv, double thr,
+                  double gamma, const double* Pic, Payload p) {
+        cr.mode = mode;
+        cr.Dv = Dv;
+        cr.thr = thr;
+        cr.gamma = gamma;
+        cr.Pic = Pic;
+        cr.p = p;
+        cr.mv_bytes = mode == 0 ? last_bytes : lap_bytes();
+        cr.j = 0;
+        cr.P[0].hf = hflag;
+        cr.P[1].hf = hflag + 4;
+        cr.P[0].e = cg_ev[0];
+        cr.P[1].e = cg_ev[1];
         {
             Timed t(prof, CCM_K_CGUPDATE);
             launch_cg_init(N, b, neg, Dv, cg, s);
         }
-        const double mv_bytes = mode == 0 ? last_bytes : lap_bytes();
         {
-            Timed t(prof, CCM_K_MATVEC, mv_bytes);
+            Timed t(prof, CCM_K_MATVEC, cr.mv_bytes);
             cg.nparts_mv = launch_matvec(g, d, qk, mode, cg.u, Pic, p, gamma, sigma, 1.0, nullptr,
                                          cg.w, cg.wu[0], CgSkip{}, s);
         }
-        // Chunks of CG iterations are issued one ahead: chunk k + 1 is
-        // enqueued before the host waits for chunk k's status, so the host's
-        // decision overlaps device work.  Launches issued after convergence
-        // return at once (device-side flag) and are timed as "other".
-        // The first chunk is sized from the previous solve's iteration count
-        // (consecutive Newton systems need similar counts), later ones are
-        // half a chunk: fewer launches are wasted after convergence.
-        const int chunk = std::max(1, o.cg_chunk);
-        const int first = std::max(2, std::min(2 * chunk, cg_pred[mode & 1]));
-        const int later = std::max(2, chunk / 2);
-        int j = 0;
-        struct Pending {
-            int j0 = 0, j1 = 0;
-            int64_t pid_end = 0;
-            std::vector<int64_t> upd, mv;
-            int* hf = nullptr;
-            hipEvent_t e = nullptr;
-        } P[2];
-        P[0].hf = hflag;
-        P[1].hf = hflag + 4;
-        P[0].e = cg_ev[0];
-        P[1].e = cg_ev[1];
-        auto issue = [&](Pending& q, int count) -> ccm_status {
-            q.j0 = j;
-            q.upd.clear();
-            q.mv.clear();
-            for (int c = 0; c < count && j < o.cg_max_iter; ++c, ++j) {
-                {
-                    Timed t(prof, CCM_K_CGUPDATE);
-                    launch_cg_update(N, j, Dv, cg, thr, s);
-                }
-                q.upd.push_back(prof.last_pair());
-                {
-                    Timed t(prof, CCM_K_MATVEC, mv_bytes);
-                    CgSkip sk;
-                    sk.rr_partials = cg.upd[(j + 1) & 1];
-                    sk.nparts = cg.nparts;
-                    sk.thr = thr;
-                    sk.done = cg.flag;
-                    launch_matvec(g, d, qk, mode, cg.u, Pic, p, gamma, sigma, 1.0, nullptr, cg.w,
-                                  cg.wu[(j + 1) & 1], sk, s);
-                }
-                q.mv.push_back(prof.last_pair());
+    }
+
+    // enqueue `count` iterations, then a copy of the status flag to q.hf
+    ccm_status cg_issue(CgPending& q, int count) {
+        q.j0 = cr.j;
+        q.upd.clear();
+        q.mv.clear();
+        for (int c = 0; c < count && cr.j < o.cg_max_iter; ++c, ++cr.j) {
+            const int j = cr.j;
+            {
+                Timed t(prof, CCM_K_CGUPDATE);
+                launch_cg_update(N, j, cr.Dv, cg, cr.thr, s);
             }
-            q.j1 = j;
-            HIPCHK(hipMemcpyAsync(q.hf, cg.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipEventRecord(q.e, s));
-            q.pid_end = prof.next_pair();
-            return CCM_OK;
-        };
-        int cur = 0;
+            q.upd.push_back(prof.last_pair());
+            {
+                Timed t(prof, CCM_K_MATVEC, cr.mv_bytes);
+                CgSkip sk;
+                sk.rr_partials = cg.upd[(j + 1) & 1];
+                sk.nparts = cg.nparts;
+                sk.thr = cr.thr;
+                sk.done = cg.flag;
+                launch_matvec(g, d, qk, cr.mode, cg.u, cr.Pic, cr.p, cr.gamma, sigma, 1.0, nullptr,
+                              cg.w, cg.wu[(j + 1) & 1], sk, s);
+            }
+            q.mv.push_back(prof.last_pair());
+        }
+        q.j1 = cr.j;
+        HIPCHK(hipMemcpyAsync(q.hf, cg.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(q.e, s));
+        q.pid_end = prof.next_pair();
+        return CCM_OK;
+    }
+
+    // launches of q issued at or after convergence (iteration done_at)
+    void cg_reclass(const CgPending& q, int done_at) {
+        for (size_t c = 0; c < q.upd.size(); ++c) {
+            const int jj = q.j0 + int(c);
+            if (jj >= done_at) prof.reclass(q.upd[c], CCM_K_OTHER);
+            if (jj + 1 >= done_at) prof.reclass(q.mv[c], CCM_K_OTHER);
+        }
+    }
+
+    // P[cur] is enqueued with its status not yet seen: wait for convergence or
+    // the iteration cap; iters = iterations taken
+    ccm_status cg_wait(int cur, int& iters) {
         bool done = false;
         int done_at = 0;
-        CHK(issue(P[0], first));
         while (true) {
-            const bool more = j < o.cg_max_iter;
-            if (more) CHK(issue(P[cur ^ 1], later));
-            HIPCHK(hipEventSynchronize(P[cur].e));
-            const Pending& q = P[cur];
+            const bool more = cr.j < o.cg_max_iter;
+            if (more) CHK(cg_issue(cr.P[cur ^ 1], cg_later()));
+            CHK(spin(cr.P[cur].e));
+            const CgPending& q = cr.P[cur];
             if (q.hf[0]) {
                 done = true;
                 done_at = q.hf[1];
-                for (size_t c = 0; c < q.upd.size(); ++c) {
-                    const int jj = q.j0 + int(c);
-                    if (jj >= done_at) prof.reclass(q.upd[c], CCM_K_OTHER);
-                    if (jj + 1 >= done_at) prof.reclass(q.mv[c], CCM_K_OTHER);
-                }
-                if (more) {
-                    const Pending& nx = P[cur ^ 1];
-                    for (size_t c = 0; c < nx.upd.size(); ++c) {
-                        prof.reclass(nx.upd[c], CCM_K_OTHER);
-                        prof.reclass(nx.mv[c], CCM_K_OTHER);
-                    }
-                }
+                cg_reclass(q, done_at);
+                if (more) cg_reclass(cr.P[cur ^ 1], 0);
             }
             prof.harvest_until(q.pid_end);
             if (done || !more) break;
             cur ^= 1;
         }
-        hflag[0] = done ? 1 : 0;
-        hflag[1] = done ? done_at : j;
-        iters = hflag[0] ? hflag[1] : j;
-        cg_pred[mode & 1] = iters + 1;
+        iters = done ? done_at : cr.j;
+        cg_pred[cr.mode & 1] = iters + 1;
         return CCM_OK;
+    }
+
+    ccm_status cg_solve(int mode, const double* b, bool neg, const double* Dv, double thr,
+                        double gamma, const double* Pic, Payload p, int& iters) {
+        cg_begin(mode, b, neg, Dv, thr, gamma, Pic, p);
+        CHK(cg_issue(cr.P[0], cg_first(mode)));
+        return cg_wait(0, iters);
     }
 
     // ---- KKT of (X, Uc) with Uc feasible up to rounding -------------------------
@@ -488,12 +558,12 @@ struct Solver::Impl {
             Timed t(prof, CCM_K_SCATTER);
             const int gp = launch_scatter(g, d, qk, 1.0, X, -1.0, A, 1.0, Uc, Gout, false, Payload{},
                                           gamma, sigma, nullptr, ps.as<double>(), s);
-            launch_finalize(ps.as<double>(), gp, kScatterNV, slot(kS), s);
+            defer_finalize(ps.as<double>(), gp, kScatterNV, slot(kS), s);
         }
         {
             Timed t(prof, CCM_K_EDGE);
             const int gp = launch_edge_kkt(g, d, qk, gamma, X, Uc, nullptr, pk.as<double>(), s);
-            launch_finalize(pk.as<double>(), gp, kEdgeKktNV, slot(kK), s);
+            defer_finalize(pk.as<double>(), gp, kEdgeKktNV, slot(kK), s);
         }
         CHK(read(kS, kK + kEdgeKktNV));
         kkt_from_slots(res);
@@ -535,17 +605,31 @@ struct Solver::Impl {
     }
 
     // ---- SSNAL at one gamma ------------------------------------------------------
+    // trial point Xt = X + alpha D with its edge pass and gradient (no wait)
+    void trial_eval(double alpha, double gamma) {
+        {
+            Timed tt(prof, CCM_K_OTHER);
+            const int gp = launch_trial(N, X, cg.x, alpha, A, G, Xt, pt.as<double>(), s);
+            defer_finalize(pt.as<double>(), gp, kAxpyNV, slot(kT), s);
+        }
+        edge_pass(Xt, Pit, plt, gamma, pet.as<double>(), kET);
+        // speculative gradient at the trial point (used if accepted)
+        scatter_grad(Xt, Pit, plt, gamma, Gt, Dinvt, pst.as<double>(), kST);
+    }
+
     ccm_status ssnal(double gamma, int& status, ccm_stats& st, double (&res)[7]) {
         const double mu = 1e-4, ls_slack = 1e-14;
         double rp_prev = INFINITY;
         status = CCM_MAX_ITER;
         bool numerical = false;
+        // values of the first outer iteration's merit function; later ones are
+        // enqueued with the KKT pass of the iteration before
+        edge_pass(X, Pi, pl, gamma, pe.as<double>(), kE);
+        scatter_grad(X, Pi, pl, gamma, G, Dinv, ps.as<double>(), kS);
+        CHK(read(kE, kS + kScatterNV));
+        Ev ev = make_ev(kE, kS);
         for (int k = 0; k < o.max_outer; ++k) {
             st.outer++;
-            edge_pass(X, Pi, pl, gamma, pe.as<double>(), kE);
-            scatter_grad(X, Pi, pl, gamma, G, Dinv, ps.as<double>(), kS);
-            CHK(read(kE, kS + kScatterNV));
-            Ev ev = make_ev(kE, kS);
             last_bytes = matvec_bytes(ev.nout);
             for (int it = 0; it < o.max_newton; ++it) {
                 if (!std::isfinite(ev.phi) || !std::isfinite(ev.gn)) {
@@ -557,11 +641,34 @@ struct Solver::Impl {
                     status = CCM_TIMEOUT;
                     return CCM_OK;
                 }
-                // Newton direction: (I + sigma B^T P B) D = -G
+                // Newton direction: (I + sigma B^T P B) D = -G.  The first
+                // chunk of CG iterations (one more than the last solve took)
+                // and the full-step trial are enqueued together; the trial's
+                // read also brings the CG status, and only if the CG needs more
+                // iterations is it continued and the trial redone.
                 const double rtol = std::min(0.1, std::pow(ev.gn, 0.2));
                 const double thr = rtol * rtol * ev.G2;
                 int iters = 0;
-                CHK(cg_solve(0, G, true, Dinv, thr, gamma, Pi, pl, iters));
+                cg_begin(0, G, true, Dinv, thr, gamma, Pi, pl);
+                CHK(cg_issue(cr.P[0], cg_first(0) + 1));
+                trial_eval(1.0, gamma);
+                CHK(read(kT, kST + kScatterNV, false));
+                if (cr.P[0].hf[0]) {
+                    iters = cr.P[0].hf[1];
+                    cg_reclass(cr.P[0], iters);
+                    cg_pred[0] = iters + 1;
+                    prof.harvest();
+                } else if (cr.j >= o.cg_max_iter) {
+                    iters = cr.j;
+                    cg_pred[0] = iters + 1;
+                    prof.harvest();
+                } else {
+                    prof.harvest();
+                    CHK(cg_issue(cr.P[1], cg_later()));
+                    CHK(cg_wait(1, iters));
+                    trial_eval(1.0, gamma);
+                    CHK(read(kT, kST + kScatterNV));
+                }
                 st.cg += iters;
                 st.newton++;
                 // Armijo backtracking on phi
@@ -570,21 +677,18 @@ struct Solver::Impl {
                 Ev evt;
                 for (int t = 0; t < 40; ++t) {
                     st.linesearch++;
-                    {
-                        Timed tt(prof, CCM_K_OTHER);
-                        const int gp = launch_trial(N, X, cg.x, alpha, A, G, Xt, pt.as<double>(), s);
-                        launch_finalize(pt.as<double>(), gp, kAxpyNV, slot(kT), s);
+                    if (t > 0) {
+                        trial_eval(alpha, gamma);
+                        CHK(read(kT, kST + kScatterNV));
                     }
-                    edge_pass(Xt, Pit, plt, gamma, pet.as<double>(), kET);
-                    // speculative gradient at the trial point (used if accepted)
-                    scatter_grad(Xt, Pit, plt, gamma, Gt, Dinvt, pst.as<double>(), kST);
-                    CHK(read(kT, kST + kScatterNV));
                     double slope = hs[kT + 1];
                     if (t == 0 && !(slope < 0.0)) {
                         // not a descent direction: fall back to steepest descent
                         launch_axpby(-1.0, G, 0.0, G, cg.x, N, s);
                         alpha = 1.0;
-                        continue;
+                        trial_eval(alpha, gamma);
+                        CHK(read(kT, kST + kScatterNV));
+                        slope = hs[kT + 1];
                     }
                     evt = make_ev(kET, kST);
                     const double slack = ls_slack * (1.0 + std::fabs(ev.phi));
@@ -607,13 +711,24 @@ struct Solver::Impl {
             // multiplier update U <- Pi_C(U + sigma B X), already in Pi
             std::swap(U, Pi);
             have_U = true;
-            // KKT at (X, U): R_D from the last gradient, the rest from one pass
+            // penalty of the next outer iteration
+            const double sigma_cur = sigma;
+            if (k >= 1 && ev.rp > 0.9 * rp_prev) sigma = std::min(o.sigma_max, 2.0 * sigma);
+            rp_prev = ev.rp;
+            // KKT at (X, U): R_D from the last gradient, the rest from one pass;
+            // the next outer iteration's edge pass and gradient are enqueued
+            // with it (discarded if this one converges)
             {
                 Timed t(prof, CCM_K_EDGE);
                 const int gp = launch_edge_kkt(g, d, qk, gamma, X, U, nullptr, pk.as<double>(), s);
-                launch_finalize(pk.as<double>(), gp, kEdgeKktNV, slot(kK), s);
+                defer_finalize(pk.as<double>(), gp, kEdgeKktNV, slot(kK), s);
             }
-            CHK(read(kK, kK + kEdgeKktNV));
+            const bool next = k + 1 < o.max_outer;
+            if (next) {
+                edge_pass(X, Pi, pl, gamma, pe.as<double>(), kE);
+                scatter_grad(X, Pi, pl, gamma, G, Dinv, ps.as<double>(), kS);
+            }
+            CHK(read(next ? kE : kK, kK + kEdgeKktNV));
             kkt_from(ev, res);
             if (!std::isfinite(res[6])) {
                 numerical = true;
@@ -630,15 +745,16 @@ struct Solver::Impl {
                 }
             }
             if (crit <= tol) {
+                sigma = sigma_cur;
                 status = CCM_CONVERGED;
                 break;
             }
             if (out_of_time()) {
+                sigma = sigma_cur;
                 status = CCM_TIMEOUT;
                 break;
             }
-            if (k >= 1 && ev.rp > 0.9 * rp_prev) sigma = std::min(o.sigma_max, 2.0 * sigma);
-            rp_prev = ev.rp;
+            if (next) ev = make_ev(kE, kS);
         }
         if (numerical) status = CCM_NUMERICAL;
         return CCM_OK;
@@ -687,7 +803,7 @@ struct Solver::Impl {
                 Timed t(prof, CCM_K_EDGE);
                 const int gp = launch_edge_admm(g, d, qk, gamma, sigma, o.tau, X, Z, L, Q,
                                                 check ? U : nullptr, pe.as<double>(), s);
-                launch_finalize(pe.as<double>(), gp, kEdgeAdmmNV, slot(kM), s);
+                defer_finalize(pe.as<double>(), gp, kEdgeAdmmNV, slot(kM), s);
             }
             if (check) {
                 CHK(kkt_of(U, gamma, G, res));
@@ -709,7 +825,7 @@ struct Solver::Impl {
                 const int gp = launch_scatter(g, d, qk, 0.0, nullptr, 0.0, nullptr, 1.0,
                                               bZold.as<double>(), T, false, Payload{}, gamma,
                                               sigma, nullptr, pm2.as<double>(), s);
-                launch_finalize(pm2.as<double>(), gp, kScatterNV, slot(kM + 4), s);
+                defer_finalize(pm2.as<double>(), gp, kScatterNV, slot(kM + 4), s);
                 CHK(read(kM, kM + 8));
                 const double rp = std::sqrt(hs[kM + 0]);
                 const double rd = sigma * std::sqrt(hs[kM + 4]);
@@ -732,7 +848,7 @@ struct Solver::Impl {
             Timed t(prof, CCM_K_EDGE);
             const int gp = launch_edge_kkt(g, d, qk, gamma, X, bL.as<double>(), U,
                                            pk.as<double>(), s);
-            launch_finalize(pk.as<double>(), gp, kEdgeKktNV, slot(kK), s);
+            defer_finalize(pk.as<double>(), gp, kEdgeKktNV, slot(kK), s);
         }
         return kkt_of(U, gamma, G, res);
     }
@@ -762,7 +878,7 @@ struct Solver::Impl {
                 Timed tt(prof, CCM_K_EDGE);
                 const int gp = launch_edge_ama(g, d, qk, gamma, nu, beta, X, U, V, pe.as<double>(),
                                                s);
-                launch_finalize(pe.as<double>(), gp, kEdgeAmaNV, slot(kM), s);
+                defer_finalize(pe.as<double>(), gp, kEdgeAmaNV, slot(kM), s);
             }
             CHK(read(kM, kM + 2));
             if (hs[kM + 0] > 0.0) {

@@ -127,8 +127,8 @@ __global__ __launch_bounds__(kBlock) void k_trial(int64_t N, const double* __res
 constexpr int kFinalizeWaves = 16;
 
 template <int NV>
-__global__ __launch_bounds__(kFinalizeWaves * 64) void k_finalize(const double* __restrict__ partials,
-                                                                  int nparts, double* __restrict__ out) {
+__device__ __forceinline__ void finalize_one(const double* __restrict__ partials, int nparts,
+                                             double* __restrict__ out) {
     const double* ptr[NV];
     int cnt[NV], st[NV];
 #pragma unroll
@@ -144,6 +144,37 @@ __global__ __launch_bounds__(kFinalizeWaves * 64) void k_finalize(const double* 
         for (int c = 0; c < NV; ++c)
             if (threadIdx.x == c) out[c] = t[c];
     }
+}
+
+template <int NV>
+__global__ __launch_bounds__(kFinalizeWaves * 64) void k_finalize(const double* __restrict__ partials,
+                                                                  int nparts, double* __restrict__ out) {
+    finalize_one<NV>(partials, nparts, out);
+}
+
+// one block per job, each reduced exactly as k_finalize reduces it
+__global__ __launch_bounds__(kFinalizeWaves * 64) void k_finalize_multi(FinalizeJobs jobs) {
+    const FinalizeJob jb = jobs.j[blockIdx.x];
+    switch (jb.nv) {
+        case 1: finalize_one<1>(jb.partials, jb.nparts, jb.out); break;
+        case 2: finalize_one<2>(jb.partials, jb.nparts, jb.out); break;
+        case 3: finalize_one<3>(jb.partials, jb.nparts, jb.out); break;
+        case 4: finalize_one<4>(jb.partials, jb.nparts, jb.out); break;
+        case 5: finalize_one<5>(jb.partials, jb.nparts, jb.out); break;
+        case 6: finalize_one<6>(jb.partials, jb.nparts, jb.out); break;
+        default: finalize_one<7>(jb.partials, jb.nparts, jb.out); break;
+    }
+}
+
+// flag[0] = 1 if any of the count values is NaN or infinite (every writer
+// stores the same value)
+__global__ __launch_bounds__(kBlock) void k_flag_nonfinite(const double* __restrict__ x,
+                                                           int64_t count, int* __restrict__ flag) {
+    bool bad = false;
+    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < count;
+         k += int64_t(gridDim.x) * kBlock)
+        bad |= !isfinite(x[k]);
+    if (bad) flag[0] = 1;
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill(double* __restrict__ x, int64_t N, double v) {
@@ -384,6 +415,17 @@ int launch_trial(int64_t N, const double* X, const double* D, double alpha, cons
     hipLaunchKernelGGL(k_trial, dim3(grid), dim3(kBlock), 0, s, N, X, D, alpha, A, G, Xt,
                        partials);
     return grid;
+}
+
+void launch_flag_nonfinite(const double* x, int64_t count, int* flag, hipStream_t s) {
+    int64_t g = (count + kBlock - 1) / kBlock;
+    g = g < 1 ? 1 : g > kMaxGrid ? kMaxGrid : g;
+    hipLaunchKernelGGL(k_flag_nonfinite, dim3(unsigned(g)), dim3(kBlock), 0, s, x, count, flag);
+}
+
+void launch_finalize_multi(const FinalizeJobs& jobs, int njobs, hipStream_t s) {
+    if (njobs > 0)
+        hipLaunchKernelGGL(k_finalize_multi, dim3(njobs), dim3(kFinalizeWaves * 64), 0, s, jobs);
 }
 
 void launch_finalize(const double* partials, int nparts, int nv, double* out, hipStream_t s) {

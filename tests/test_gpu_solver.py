@@ -139,6 +139,38 @@ def test_invalid_arguments():
     An[2, 1] = np.nan
     with pytest.raises(ccm.CcmError):
         ccm.ccm_solve_path(dev(An), s, d_, w, [0.1], 2.0, 1e-6)
+    An[2, 1] = -np.inf
+    with pytest.raises(ccm.CcmError) as e:
+        ccm.ccm_solve_path(dev(An), s, d_, w, [0.1], 2.0, 1e-6)
+    assert e.value.status == 1
+
+
+def test_nonfinite_points_rejected_anywhere_in_a_large_array():
+    # the device finiteness pass strides over more values than its grid has
+    # threads: a bad value in the last row is still found
+    torch, ccm = need_gpu()
+    n, d = 40000, 64
+    A = np.random.default_rng(3).normal(size=(n, d))
+    for bad in (np.nan, np.inf):
+        A2 = A.copy()
+        A2[-1, -1] = bad
+        with pytest.raises(ccm.CcmError) as e:
+            ccm.ccm_build_knn_graph(dev(A2), 5, 0.0)
+        assert e.value.status == 1
+    s, d_, w, _ = ccm.ccm_build_knn_graph(dev(A), 5, 0.0)
+    assert s.numel() >= n * 5 // 2
+
+
+def test_release_workspace_between_solves_keeps_results():
+    torch, ccm = need_gpu()
+    A, _ = synthdata.blobs2d(n_per=30)
+    src, dst, w, *_ = oracle.knn_graph(A, 6, 0.5)
+    g = [0.05, 0.3]
+    one = ccm.ccm_solve_path(dev(A), *graph_dev(src, dst, w), g, 2.0, 1e-8)
+    ccm.ccm_release_workspace()
+    two = ccm.ccm_solve_path(dev(A), *graph_dev(src, dst, w), g, 2.0, 1e-8)
+    assert np.array_equal(host(one["X"]), host(two["X"]))
+    ccm.ccm_release_workspace()
 
 
 def test_max_iter_status_and_time_budget():
