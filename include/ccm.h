@@ -14,11 +14,13 @@
  *    unless the name ends in _host.  Dense matrices are row-major FP64:
  *    A and X are n x d (row i = point i), U is m x d (row l = edge l).
  *  - The caller owns every buffer; the library never frees caller memory.
- *    Work space is allocated on the given stream (stream-ordered) from a
- *    memory pool the library keeps on each device, and handed back to that
- *    pool before the call returns; the pool keeps it reserved for later
- *    calls until ccm_release_workspace().  All work is enqueued on `stream`;
- *    calls that return host values synchronise that stream.
+ *    Work space is device memory that the library caches per device: a call
+ *    takes blocks from the cache (or allocates them), uses them in the order
+ *    of `stream` and returns them to the cache before it returns, so later
+ *    calls reuse them without allocating.  The cache holds at most half of
+ *    the device's memory; ccm_release_workspace() frees it.  All work is
+ *    enqueued on `stream`; calls that return host values synchronise that
+ *    stream.
  *  - Edges: l = (src_l, dst_l) is an undirected edge with weight w_l.  On
  *    input any order and orientation is accepted; self-loops and zero
  *    weights are dropped and duplicate pairs are merged by adding their
@@ -65,9 +67,9 @@ const char* ccm_status_string(ccm_status s);
 const char* ccm_last_error(void);
 const char* ccm_version(void);
 
-/* Returns to the driver the device memory that the library's pools hold in
- * reserve (work space freed by earlier calls, on every device used so far).
- * Memory of work still in flight is kept.  CCM_E_HIP if a pool call fails. */
+/* Frees the work space the library caches (on every device used so far),
+ * after the work that last used each block has finished.  Blocks in use by
+ * a call running on another thread are kept.  CCM_E_HIP if a HIP call fails. */
 ccm_status ccm_release_workspace(void);
 
 /* ---------------------------------------------------------------------------

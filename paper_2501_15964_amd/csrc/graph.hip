@@ -4,6 +4,9 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <utility>
+#include <unordered_map>
+#include <map>
 #include <vector>
 
 #include "graph.hpp"
@@ -115,51 +118,139 @@ __global__ __launch_bounds__(kBlock) void k_epos(int64_t cnt, const Inc* __restr
 
 namespace {
 constexpr int kMaxDev = 64;
-struct PoolTable {
-    std::mutex mu;
-    hipMemPool_t pools[kMaxDev] = {};
-    bool tried[kMaxDev] = {};
+
+struct CachedBlock {
+    void* p;
+    hipStream_t s;   // stream of the last use
+    hipEvent_t ev;   // recorded on s when the block was freed
 };
-PoolTable& pool_table() {
-    static PoolTable t;
-    return t;
+
+struct DevCache {
+    std::mutex mu;
+    std::multimap<size_t, CachedBlock> free_blocks;            // by size class
+    std::unordered_map<void*, std::pair<size_t, hipEvent_t>> live;
+    size_t cached = 0;  // bytes in free_blocks
+    size_t cap = 0;     // limit on `cached` (0: not yet known)
+};
+
+DevCache& dev_cache(int dev) {
+    static DevCache caches[kMaxDev];
+    return caches[dev];
+}
+
+size_t size_class(size_t b) {
+    if (b <= 256) return 256;
+    if (b < (size_t(1) << 20)) {
+        size_t c = 512;
+        while (c < b) c <<= 1;
+        return c;
+    }
+    const size_t mb = size_t(1) << 20;
+    return (b + mb - 1) / mb * mb;
+}
+
+// frees every cached block of c (caller holds c.mu)
+hipError_t drop_cached(DevCache& c) {
+    hipError_t r = hipSuccess;
+    for (auto& kv : c.free_blocks) {
+        CachedBlock& b = kv.second;
+        if (b.ev) {
+            const hipError_t e = hipEventSynchronize(b.ev);
+            if (e != hipSuccess) r = e;
+            (void)hipEventDestroy(b.ev);
+        }
+        const hipError_t f = hipFree(b.p);
+        if (f != hipSuccess) r = f;
+    }
+    c.free_blocks.clear();
+    c.cached = 0;
+    return r;
 }
 }  // namespace
 
-hipMemPool_t workspace_pool() {
-    PoolTable& t = pool_table();
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return nullptr;
-    std::lock_guard<std::mutex> lk(t.mu);
-    if (!t.tried[dev]) {
-        t.tried[dev] = true;
-        hipMemPoolProps pr;
-        std::memset(&pr, 0, sizeof(pr));
-        pr.allocType = hipMemAllocationTypePinned;
-        pr.handleTypes = hipMemHandleTypeNone;
-        pr.location.type = hipMemLocationTypeDevice;
-        pr.location.id = dev;
-        hipMemPool_t p = nullptr;
-        if (hipMemPoolCreate(&p, &pr) == hipSuccess) {
-            uint64_t keep = UINT64_MAX;
-            if (hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess)
-                t.pools[dev] = p;
-            else
-                (void)hipMemPoolDestroy(p);
+hipError_t workspace_alloc(void** p, size_t bytes, hipStream_t s, int& dev) {
+    *p = nullptr;
+    dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+    DevCache& c = dev_cache(dev);
+    const size_t cls = size_class(bytes);
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto range = c.free_blocks.equal_range(cls);
+    if (range.first != range.second) {
+        auto it = range.first;
+        for (auto j = range.first; j != range.second; ++j)
+            if (j->second.s == s) {
+                it = j;
+                break;
+            }
+        CachedBlock b = it->second;
+        // another stream's last use must finish before this stream's work
+        if (b.s != s && b.ev) {
+            e = hipStreamWaitEvent(s, b.ev, 0);
+            if (e != hipSuccess) return e;
         }
+        c.free_blocks.erase(it);
+        c.cached -= cls;
+        c.live[b.p] = {cls, b.ev};
+        *p = b.p;
+        return hipSuccess;
     }
-    return t.pools[dev];
+    e = hipMalloc(p, cls);
+    if (e == hipErrorOutOfMemory && !c.free_blocks.empty()) {
+        (void)hipGetLastError();
+        (void)drop_cached(c);
+        e = hipMalloc(p, cls);
+    }
+    if (e != hipSuccess) return e;
+    c.live[*p] = {cls, nullptr};
+    return hipSuccess;
+}
+
+void workspace_free(void* p, hipStream_t s, int dev) {
+    if (!p || dev < 0 || dev >= kMaxDev) return;
+    DevCache& c = dev_cache(dev);
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return;  // not a block of this device's cache
+    const size_t cls = it->second.first;
+    hipEvent_t ev = it->second.second;
+    c.live.erase(it);
+    if (c.cap == 0) {
+        size_t fr = 0, tot = 0;
+        c.cap = hipMemGetInfo(&fr, &tot) == hipSuccess ? tot / 2 : (size_t(8) << 30);
+    }
+    bool keep = c.cached + cls <= c.cap;
+    if (keep && !ev) keep = hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+    if (keep) keep = hipEventRecord(ev, s) == hipSuccess;
+    if (!keep) {
+        // over the cap (or no event): hipFree waits for the device
+        if (ev) (void)hipEventDestroy(ev);
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        if (cur != dev) (void)hipSetDevice(dev);
+        (void)hipFree(p);
+        if (cur != dev) (void)hipSetDevice(cur);
+        return;
+    }
+    c.free_blocks.insert({cls, CachedBlock{p, s, ev}});
+    c.cached += cls;
 }
 
 hipError_t release_workspace() {
-    PoolTable& t = pool_table();
-    std::lock_guard<std::mutex> lk(t.mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
     hipError_t r = hipSuccess;
     for (int dv = 0; dv < kMaxDev; ++dv) {
-        if (!t.pools[dv]) continue;
-        const hipError_t e = hipMemPoolTrimTo(t.pools[dv], 0);
+        DevCache& c = dev_cache(dv);
+        std::lock_guard<std::mutex> lk(c.mu);
+        if (c.free_blocks.empty()) continue;
+        if (hipSetDevice(dv) != hipSuccess) continue;
+        const hipError_t e = drop_cached(c);
         if (e != hipSuccess) r = e;
     }
+    (void)hipSetDevice(cur);
     return r;
 }
 

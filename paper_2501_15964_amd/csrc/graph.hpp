@@ -8,32 +8,33 @@
 
 namespace ccm {
 
-// The library's memory pool on the current device (created on first use):
-// stream-ordered workspace comes from it, and what one call frees stays
-// reserved for the next instead of going back to the driver at every
-// synchronisation.  nullptr if the device offers no pools.
-hipMemPool_t workspace_pool();
-// Returns the unused reserve of every pool created so far to the driver.
+// Device work space of the library: blocks are cached per device after use
+// and handed out again (same stream: at once; another stream: after an
+// event wait), so repeated calls neither map nor unmap memory.  Sizes are
+// rounded up to size classes.  The cache keeps at most half of the device's
+// memory; release_workspace() frees every cached block.
+hipError_t workspace_alloc(void** p, size_t bytes, hipStream_t s, int& dev);
+void workspace_free(void* p, hipStream_t s, int dev);
 hipError_t release_workspace();
 
 // Stream-ordered device allocation that is released when the object dies.
 struct DevMem {
     void* p = nullptr;
     hipStream_t s = nullptr;
+    int dev = 0;  // device of the block
     DevMem() = default;
     DevMem(const DevMem&) = delete;
     DevMem& operator=(const DevMem&) = delete;
     ~DevMem() { release(); }
     void release() {
-        if (p) (void)hipFreeAsync(p, s);
+        if (p) workspace_free(p, s, dev);
         p = nullptr;
     }
     hipError_t alloc(size_t bytes, hipStream_t st) {
         release();
         s = st;
         if (bytes == 0) bytes = 8;
-        hipMemPool_t pool = workspace_pool();
-        return pool ? hipMallocFromPoolAsync(&p, bytes, pool, st) : hipMallocAsync(&p, bytes, st);
+        return workspace_alloc(&p, bytes, st, dev);
     }
     template <class T>
     T* as() const { return static_cast<T*>(p); }
