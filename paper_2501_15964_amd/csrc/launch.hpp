@@ -281,6 +281,7 @@ void launch_rowscale(const double* x, const double* rs, double* out, int64_t row
 size_t labels_temp_bytes(int64_t n);
 void launch_labels(int64_t n, int64_t m, const int* src, const int* dst, const int* fused,
                    int* parent, int* rank, void* temp, size_t temp_bytes, int* labels,
-                   int* n_clusters, hipStream_t s);
+                   int* n_clusters, hipStream_t s,
+                   const int* inc_ptr = nullptr, const Inc* inc = nullptr);
 
 }  // namespace ccm

@@ -974,7 +974,7 @@ struct Solver::Impl {
             lab = scratch.as<int>();
         }
         launch_labels(n, m, g.src, g.dst, fused.as<int>(), parent.as<int>(), rank.as<int>(),
-                      ltemp.p, ltemp_bytes, lab, cgflag.as<int>() + 2, s);
+                      ltemp.p, ltemp_bytes, lab, cgflag.as<int>() + 2, s, g.inc_ptr, g.inc);
         HIPCHK(hipMemcpyAsync(hflag + 2, cgflag.as<int>() + 2, sizeof(int), hipMemcpyDeviceToHost,
                               s));
         HIPCHK(hipStreamSynchronize(s));
