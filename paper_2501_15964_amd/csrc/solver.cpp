@@ -711,9 +711,13 @@ struct Solver::Impl {
             // multiplier update U <- Pi_C(U + sigma B X), already in Pi
             std::swap(U, Pi);
             have_U = true;
-            // penalty of the next outer iteration
+            // penalty of the next outer iteration: doubled when the primal
+            // residual fell by less than a factor (2 for q = 2, whose Newton
+            // systems stay well conditioned as sigma grows; 1/0.9 for q = 1
+            // and inf, where a faster growth multiplies the CG iterations)
             const double sigma_cur = sigma;
-            if (k >= 1 && ev.rp > 0.9 * rp_prev) sigma = std::min(o.sigma_max, 2.0 * sigma);
+            const double stall = qk == kQ2 ? 0.5 : 0.9;
+            if (k >= 1 && ev.rp > stall * rp_prev) sigma = std::min(o.sigma_max, 2.0 * sigma);
             rp_prev = ev.rp;
             // KKT at (X, U): R_D from the last gradient, the rest from one pass;
             // the next outer iteration's edge pass and gradient are enqueued
