@@ -1,9 +1,13 @@
 // C ABI entry points of libccm (declared in include/ccm.h): argument checks,
 // error reporting and dispatch to the device graph, solvers and kernels.
+#include <algorithm>
+#include <atomic>
 #include <cmath>
-#include <map>
 #include <cstring>
+#include <map>
+#include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "knn.hpp"
@@ -75,6 +79,86 @@ ccm_options defaults() {
     o.tau = 1.618;
     o.time_budget_s = 0.0;
     return o;
+}
+
+// concurrent (q, d) groups of ccm_solve_path_batched
+constexpr int kBatchedStreams = 4;
+
+// One (q, d) group of batched instances: their block-diagonal union solved
+// by one Solver on stream `stream`.  Errors set g_err of the calling thread.
+ccm_status solve_group(const ccm_instance* inst_host, const std::vector<int>& ids, int qk, int d,
+                       const double* A_all, const int32_t* src_all, const int32_t* dst_all,
+                       const double* w_all, const double* gammas_host, int32_t n_gamma,
+                       double tol, const ccm_options& o, double* X_out_all, int32_t* labels_all,
+                       int32_t* n_clusters_host, double* kkt_host, int32_t* status_host,
+                       hipStream_t stream) {
+    const int S = int(ids.size());
+    BatchSpec b;
+    b.S = S;
+    b.vseg.assign(S + 1, 0);
+    b.eseg.assign(S + 1, 0);
+    std::vector<int64_t> xoff(S), loff(S);
+    for (int k = 0; k < S; ++k) {
+        const ccm_instance& I = inst_host[ids[k]];
+        b.vseg[k + 1] = b.vseg[k] + I.n;
+        b.eseg[k + 1] = b.eseg[k] + I.m;
+        xoff[k] = I.x_offset;
+        loff[k] = I.l_offset;
+    }
+    const int64_t nU = b.vseg[S], mU = b.eseg[S];
+    if (nU > (int64_t(1) << 30) || mU > (int64_t(1) << 30))
+        return fail(CCM_E_INVALID, "batched group too large");
+    DevMem Au, su, du, wu, seg, bad;
+    HIPCHK_API(Au.alloc(size_t(nU) * d * 8, stream));
+    HIPCHK_API(su.alloc(size_t(std::max<int64_t>(mU, 1)) * 4, stream));
+    HIPCHK_API(du.alloc(size_t(std::max<int64_t>(mU, 1)) * 4, stream));
+    HIPCHK_API(wu.alloc(size_t(std::max<int64_t>(mU, 1)) * 8, stream));
+    HIPCHK_API(seg.alloc(size_t(4 * S + 2) * 8, stream));
+    HIPCHK_API(bad.alloc(4, stream));
+    HIPCHK_API(hipMemsetAsync(bad.p, 0, 4, stream));
+    for (int k = 0; k < S; ++k) {
+        const ccm_instance& I = inst_host[ids[k]];
+        HIPCHK_API(hipMemcpyAsync(Au.as<double>() + b.vseg[k] * d, A_all + I.a_offset,
+                                  size_t(I.n) * d * 8, hipMemcpyDeviceToDevice, stream));
+        launch_offset_edges(I.m, src_all + I.e_offset, dst_all + I.e_offset,
+                            w_all + I.e_offset, int(b.vseg[k]), int(I.n),
+                            su.as<int>() + b.eseg[k], du.as<int>() + b.eseg[k],
+                            wu.as<double>() + b.eseg[k], bad.as<int>(), stream);
+    }
+    int64_t* sd = seg.as<int64_t>();
+    HIPCHK_API(hipMemcpyAsync(sd, b.vseg.data(), size_t(S + 1) * 8, hipMemcpyHostToDevice,
+                              stream));
+    HIPCHK_API(hipMemcpyAsync(sd + (S + 1), b.eseg.data(), size_t(S + 1) * 8,
+                              hipMemcpyHostToDevice, stream));
+    HIPCHK_API(hipMemcpyAsync(sd + 2 * (S + 1), xoff.data(), size_t(S) * 8,
+                              hipMemcpyHostToDevice, stream));
+    HIPCHK_API(hipMemcpyAsync(sd + 2 * (S + 1) + S, loff.data(), size_t(S) * 8,
+                              hipMemcpyHostToDevice, stream));
+    int hbad = 0;
+    HIPCHK_API(hipMemcpyAsync(&hbad, bad.p, 4, hipMemcpyDeviceToHost, stream));
+    HIPCHK_API(hipStreamSynchronize(stream));
+    if (hbad) return fail(CCM_E_INVALID, "instance edges must be canonical with local endpoints");
+    ccm_status st = check_finite(Au.as<double>(), nU * d, stream, "A");
+    if (st != CCM_OK) return st;
+    b.vseg_dev = sd;
+    b.eseg_dev = sd + (S + 1);
+    b.xoff_dev = sd + 2 * (S + 1);
+    b.loff_dev = sd + 2 * (S + 1) + S;
+    b.inst = ids;
+    b.X_out_all = X_out_all;
+    b.labels_all = labels_all;
+    b.n_clusters_host = n_clusters_host;
+    b.kkt_host = kkt_host;
+    b.status_host = status_host;
+    std::string err;
+    OwnedGraph og;
+    st = graph_build(su.as<int>(), du.as<int>(), wu.as<double>(), mU, nU, d, true, stream, og,
+                     err);
+    if (st != CCM_OK) return fail(st, err);
+    Solver solver(og.g, d, qk, Au.as<double>(), stream, o, tol, err);
+    st = solver.run_batched(gammas_host, n_gamma, b);
+    if (st != CCM_OK) return fail(st, err);
+    return CCM_OK;
 }
 
 }  // namespace
@@ -250,77 +334,82 @@ ccm_status ccm_solve_path_batched(const ccm_instance* inst_host, int32_t n_inst,
         groups[{qk, I.d}].push_back(i);
     }
     if (n_gamma == 0) return CCM_OK;
+    // Groups are independent problems; each is latency-bound on its own
+    // (small kernels and host round trips), so several run at once, each on
+    // a stream of its own, largest first.
+    std::vector<std::pair<int, const std::vector<int>*>> order;  // (key index, members)
+    std::vector<std::pair<int, int64_t>> keys;
+    std::vector<double> work;
     for (auto& kv : groups) {
-        const int qk = kv.first.first;
-        const int d = int(kv.first.second);
-        const std::vector<int>& ids = kv.second;
-        const int S = int(ids.size());
-        BatchSpec b;
-        b.S = S;
-        b.vseg.assign(S + 1, 0);
-        b.eseg.assign(S + 1, 0);
-        std::vector<int64_t> xoff(S), loff(S);
-        for (int k = 0; k < S; ++k) {
-            const ccm_instance& I = inst_host[ids[k]];
-            b.vseg[k + 1] = b.vseg[k] + I.n;
-            b.eseg[k + 1] = b.eseg[k] + I.m;
-            xoff[k] = I.x_offset;
-            loff[k] = I.l_offset;
-        }
-        const int64_t nU = b.vseg[S], mU = b.eseg[S];
-        if (nU > (int64_t(1) << 30) || mU > (int64_t(1) << 30))
-            return fail(CCM_E_INVALID, "batched group too large");
-        DevMem Au, su, du, wu, seg, bad;
-        HIPCHK_API(Au.alloc(size_t(nU) * d * 8, stream));
-        HIPCHK_API(su.alloc(size_t(std::max<int64_t>(mU, 1)) * 4, stream));
-        HIPCHK_API(du.alloc(size_t(std::max<int64_t>(mU, 1)) * 4, stream));
-        HIPCHK_API(wu.alloc(size_t(std::max<int64_t>(mU, 1)) * 8, stream));
-        HIPCHK_API(seg.alloc(size_t(4 * S + 2) * 8, stream));
-        HIPCHK_API(bad.alloc(4, stream));
-        HIPCHK_API(hipMemsetAsync(bad.p, 0, 4, stream));
-        for (int k = 0; k < S; ++k) {
-            const ccm_instance& I = inst_host[ids[k]];
-            HIPCHK_API(hipMemcpyAsync(Au.as<double>() + b.vseg[k] * d, A_all + I.a_offset,
-                                      size_t(I.n) * d * 8, hipMemcpyDeviceToDevice, stream));
-            launch_offset_edges(I.m, src_all + I.e_offset, dst_all + I.e_offset,
-                                w_all + I.e_offset, int(b.vseg[k]), int(I.n),
-                                su.as<int>() + b.eseg[k], du.as<int>() + b.eseg[k],
-                                wu.as<double>() + b.eseg[k], bad.as<int>(), stream);
-        }
-        int64_t* sd = seg.as<int64_t>();
-        HIPCHK_API(hipMemcpyAsync(sd, b.vseg.data(), size_t(S + 1) * 8, hipMemcpyHostToDevice,
-                                  stream));
-        HIPCHK_API(hipMemcpyAsync(sd + (S + 1), b.eseg.data(), size_t(S + 1) * 8,
-                                  hipMemcpyHostToDevice, stream));
-        HIPCHK_API(hipMemcpyAsync(sd + 2 * (S + 1), xoff.data(), size_t(S) * 8,
-                                  hipMemcpyHostToDevice, stream));
-        HIPCHK_API(hipMemcpyAsync(sd + 2 * (S + 1) + S, loff.data(), size_t(S) * 8,
-                                  hipMemcpyHostToDevice, stream));
-        int hbad = 0;
-        HIPCHK_API(hipMemcpyAsync(&hbad, bad.p, 4, hipMemcpyDeviceToHost, stream));
-        HIPCHK_API(hipStreamSynchronize(stream));
-        if (hbad) return fail(CCM_E_INVALID, "instance edges must be canonical with local endpoints");
-        ccm_status st = check_finite(Au.as<double>(), nU * d, stream, "A");
-        if (st != CCM_OK) return st;
-        b.vseg_dev = sd;
-        b.eseg_dev = sd + (S + 1);
-        b.xoff_dev = sd + 2 * (S + 1);
-        b.loff_dev = sd + 2 * (S + 1) + S;
-        b.inst = ids;
-        b.X_out_all = X_out_all;
-        b.labels_all = labels_all;
-        b.n_clusters_host = n_clusters_host;
-        b.kkt_host = kkt_host;
-        b.status_host = status_host;
-        std::string err;
-        OwnedGraph og;
-        st = graph_build(su.as<int>(), du.as<int>(), wu.as<double>(), mU, nU, d, true, stream, og,
-                         err);
-        if (st != CCM_OK) return fail(st, err);
-        Solver solver(og.g, d, qk, Au.as<double>(), stream, o, tol, err);
-        st = solver.run_batched(gammas_host, n_gamma, b);
-        if (st != CCM_OK) return fail(st, err);
+        double wk = 0;
+        for (int i : kv.second) wk += double(inst_host[i].m + inst_host[i].n) * double(kv.first.second);
+        keys.push_back(kv.first);
+        order.push_back({int(keys.size()) - 1, &kv.second});
+        work.push_back(wk);
     }
+    std::sort(order.begin(), order.end(),
+              [&](const auto& a, const auto& b) { return work[a.first] > work[b.first]; });
+    auto run_group = [&](int k, hipStream_t gs) -> ccm_status {
+        const int qk = keys[order[k].first].first;
+        const int d = int(keys[order[k].first].second);
+        const std::vector<int>& ids = *order[k].second;
+        return solve_group(inst_host, ids, qk, d, A_all, src_all, dst_all, w_all, gammas_host,
+                           n_gamma, tol, o, X_out_all, labels_all, n_clusters_host, kkt_host,
+                           status_host, gs);
+    };
+    int dev = 0;
+    HIPCHK_API(hipGetDevice(&dev));
+    hipEvent_t ready = nullptr;
+    HIPCHK_API(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    struct EvFree {
+        hipEvent_t e;
+        ~EvFree() { (void)hipEventDestroy(e); }
+    } evf{ready};
+    HIPCHK_API(hipEventRecord(ready, stream));
+    const int G = int(order.size());
+    const int nthreads = std::min(G, kBatchedStreams);
+    std::vector<ccm_status> gst(static_cast<size_t>(G), CCM_OK);
+    std::vector<std::string> gerr(static_cast<size_t>(G));
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+        if (hipSetDevice(dev) != hipSuccess) return;
+        hipStream_t gs = nullptr;
+        if (hipStreamCreateWithFlags(&gs, hipStreamNonBlocking) != hipSuccess) {
+            const int k = next++;
+            if (k < G) {
+                gst[k] = CCM_E_HIP;
+                gerr[k] = "hipStreamCreateWithFlags failed";
+            }
+            return;
+        }
+        (void)hipStreamWaitEvent(gs, ready, 0);
+        for (int k = next++; k < G; k = next++) {
+            ccm_status st = CCM_OK;
+            try {
+                st = run_group(k, gs);
+            } catch (const std::bad_alloc&) {
+                st = fail(CCM_E_NOMEM, "host allocation failed");
+            } catch (...) {
+                st = fail(CCM_E_HIP, "unexpected exception in a batched group");
+            }
+            if (st != CCM_OK) {
+                gst[k] = st;
+                gerr[k] = g_err;
+            }
+            if (hipStreamSynchronize(gs) != hipSuccess && gst[k] == CCM_OK) {
+                gst[k] = CCM_E_HIP;
+                gerr[k] = "group stream failed";
+            }
+        }
+        (void)hipStreamSynchronize(gs);
+        (void)hipStreamDestroy(gs);
+    };
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nthreads; ++t) pool.emplace_back(worker);
+    for (auto& th : pool) th.join();
+    if (next.load() < G) return fail(CCM_E_HIP, "batched worker threads did not start");
+    for (int k = 0; k < G; ++k)
+        if (gst[k] != CCM_OK) return fail(gst[k], gerr[k]);
     HIPCHK_API(hipStreamSynchronize(stream));
     return CCM_OK;
 }

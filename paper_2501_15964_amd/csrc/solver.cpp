@@ -619,6 +619,9 @@ struct Solver::Impl {
 
     ccm_status ssnal(double gamma, int& status, ccm_stats& st, double (&res)[7]) {
         const double mu = 1e-4, ls_slack = 1e-14;
+        // inner Newton stop: gradient norm below this fraction of R_P (q = inf
+        // takes a looser inner solve and a slower penalty growth, below)
+        const double inner = qk == kQInf ? 0.5 : 0.2;
         double rp_prev = INFINITY;
         status = CCM_MAX_ITER;
         bool numerical = false;
@@ -636,7 +639,7 @@ struct Solver::Impl {
                     numerical = true;
                     break;
                 }
-                if (ev.gn <= std::max(0.5 * tol * floor_scale, 0.2 * ev.rp)) break;
+                if (ev.gn <= std::max(0.5 * tol * floor_scale, inner * ev.rp)) break;
                 if (out_of_time()) {
                     status = CCM_TIMEOUT;
                     return CCM_OK;
@@ -714,9 +717,10 @@ struct Solver::Impl {
             // penalty of the next outer iteration: doubled when the primal
             // residual fell by less than a factor (2 for q = 2, whose Newton
             // systems stay well conditioned as sigma grows; 1/0.9 for q = 1
-            // and inf, where a faster growth multiplies the CG iterations)
+            // and 1/0.95 for q = inf, where a faster growth multiplies the CG
+            // iterations)
             const double sigma_cur = sigma;
-            const double stall = qk == kQ2 ? 0.5 : 0.9;
+            const double stall = qk == kQ2 ? 0.5 : qk == kQ1 ? 0.9 : 0.95;
             if (k >= 1 && ev.rp > stall * rp_prev) sigma = std::min(o.sigma_max, 2.0 * sigma);
             rp_prev = ev.rp;
             // KKT at (X, U): R_D from the last gradient, the rest from one pass;

@@ -310,6 +310,29 @@ def test_batched_matches_single_instance_solves():
                 assert res[k]["n_clusters"][t] == ref["n_clusters"][t]
 
 
+def test_batched_groups_concurrent_and_reproducible():
+    # the (q, d) groups run at once on streams of their own: results are the
+    # same run to run and when the call is made on a side stream whose own
+    # work produced the inputs just before
+    torch, ccm = need_gpu()
+    insts = _instances(12, seed=23)
+    assert len({(i["q"], i["A"].shape[1]) for i in insts}) >= 5
+    gammas = synthdata.gamma_grid(-2, 0.5, 3)
+    dev_insts = [dict(A=dev(i["A"]), src=dev(i["src"].astype(np.int32)),
+                      dst=dev(i["dst"].astype(np.int32)), w=dev(i["w"]), q=i["q"]) for i in insts]
+    one = ccm.ccm_solve_path_batched(dev_insts, gammas, 1e-8)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        moved = [dict(x, A=x["A"] * 1.0) for x in dev_insts]
+        two = ccm.ccm_solve_path_batched(moved, gammas, 1e-8, stream=side)
+    side.synchronize()
+    for a, b in zip(one, two):
+        assert np.array_equal(host(a["X"]), host(b["X"]))
+        assert np.array_equal(host(a["labels"]), host(b["labels"]))
+        assert np.array_equal(np.asarray(a["status"]), np.asarray(b["status"]))
+        assert np.all(np.asarray(a["status"]) == 0)
+
+
 def test_batched_rejects_bad_descriptor():
     torch, ccm = need_gpu()
     insts = _instances(2, seed=22)
