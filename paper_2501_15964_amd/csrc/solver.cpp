@@ -373,18 +373,26 @@ struct Solver::Impl {
     }
 
     // ---- shared pieces -------------------------------------------------------
-    void edge_pass(const double* Xc, double* Pic, Payload p, double gamma, double* part,
-                   int slot_out) {
+    // The SSNAL edge pass (Pi, payload, merit terms) and the gradient G with
+    // the Jacobi diagonal.  q = 1, 2: one vertex-centric launch in which both
+    // endpoints of an edge project its row (a clamp or a scaling).  q = inf:
+    // the edge-parallel pass then the vertex scatter, since its l1-ball
+    // projection (an iteration) costs more twice than Pi's extra read.
+    void edge_grad(const double* Xc, double* Pic, Payload p, double gamma, double* Gc, double* Dc,
+                   double* epart, double* spart, int eslot, int sslot) {
         Timed t(prof, CCM_K_EDGE);
-        const int gp = launch_edge_ssnal(g, d, qk, gamma, sigma, Xc, U, Pic, p, part, s);
-        defer_finalize(part, gp, kEdgeSsnalNV, slot(slot_out), s);
-    }
-    void scatter_grad(const double* Xc, const double* Pic, Payload p, double gamma, double* Gc,
-                      double* Dc, double* part, int slot_out) {
-        Timed t(prof, CCM_K_SCATTER);
-        const int gp = launch_scatter(g, d, qk, 1.0, Xc, -1.0, A, 1.0, Pic, Gc, true, p, gamma, sigma,
-                                      Dc, part, s);
-        defer_finalize(part, gp, kScatterNV, slot(slot_out), s);
+        if (qk != kQInf) {
+            const int gp = launch_edge_grad(g, d, qk, gamma, sigma, Xc, U, A, Pic, p, Gc, Dc,
+                                            epart, spart, s);
+            defer_finalize(epart, gp, kEdgeSsnalNV, slot(eslot), s);
+            defer_finalize(spart, gp, kScatterNV, slot(sslot), s);
+            return;
+        }
+        const int ge = launch_edge_ssnal(g, d, qk, gamma, sigma, Xc, U, Pic, p, epart, s);
+        defer_finalize(epart, ge, kEdgeSsnalNV, slot(eslot), s);
+        const int gs = launch_scatter(g, d, qk, 1.0, Xc, -1.0, A, 1.0, Pic, Gc, true, p, gamma,
+                                      sigma, Dc, spart, s);
+        defer_finalize(spart, gs, kScatterNV, slot(sslot), s);
     }
     Ev make_ev(int e, int sc) const {
         Ev v;
@@ -612,9 +620,8 @@ struct Solver::Impl {
             const int gp = launch_trial(N, X, cg.x, alpha, A, G, Xt, pt.as<double>(), s);
             defer_finalize(pt.as<double>(), gp, kAxpyNV, slot(kT), s);
         }
-        edge_pass(Xt, Pit, plt, gamma, pet.as<double>(), kET);
-        // speculative gradient at the trial point (used if accepted)
-        scatter_grad(Xt, Pit, plt, gamma, Gt, Dinvt, pst.as<double>(), kST);
+        // with the gradient at the trial point (used if accepted)
+        edge_grad(Xt, Pit, plt, gamma, Gt, Dinvt, pet.as<double>(), pst.as<double>(), kET, kST);
     }
 
     ccm_status ssnal(double gamma, int& status, ccm_stats& st, double (&res)[7]) {
@@ -627,8 +634,7 @@ struct Solver::Impl {
         bool numerical = false;
         // values of the first outer iteration's merit function; later ones are
         // enqueued with the KKT pass of the iteration before
-        edge_pass(X, Pi, pl, gamma, pe.as<double>(), kE);
-        scatter_grad(X, Pi, pl, gamma, G, Dinv, ps.as<double>(), kS);
+        edge_grad(X, Pi, pl, gamma, G, Dinv, pe.as<double>(), ps.as<double>(), kE, kS);
         CHK(read(kE, kS + kScatterNV));
         Ev ev = make_ev(kE, kS);
         for (int k = 0; k < o.max_outer; ++k) {
@@ -732,10 +738,7 @@ struct Solver::Impl {
                 defer_finalize(pk.as<double>(), gp, kEdgeKktNV, slot(kK), s);
             }
             const bool next = k + 1 < o.max_outer;
-            if (next) {
-                edge_pass(X, Pi, pl, gamma, pe.as<double>(), kE);
-                scatter_grad(X, Pi, pl, gamma, G, Dinv, ps.as<double>(), kS);
-            }
+            if (next) edge_grad(X, Pi, pl, gamma, G, Dinv, pe.as<double>(), ps.as<double>(), kE, kS);
             CHK(read(next ? kE : kK, kK + kEdgeKktNV));
             kkt_from(ev, res);
             if (!std::isfinite(res[6])) {

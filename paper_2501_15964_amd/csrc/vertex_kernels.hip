@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include "launch.hpp"
+#include "proj.hpp"
 
 namespace ccm {
 namespace {
@@ -388,6 +389,201 @@ __global__ __launch_bounds__(kBlock) void k_scatter_win(DevGraph g, int d, Scatt
     block_reduce_store<kScatterNV>(acc4, partials + blockIdx.x * kScatterNV);
 }
 
+// ---- SSNAL edge pass fused with the gradient -----------------------------------
+// For every incidence of vertex v on edge l = (i, j): y_l = u_l + sigma (x_i -
+// x_j) and its projection Pi_l, recomputed by both endpoints from the same
+// operands in the same order (so bit-identical); the signed Pi_l enters
+// G_v = x_v - a_v + (B^T Pi)_v and the Jacobi diagonal of I + sigma B^T P B.
+// The first endpoint alone stores Pi_l, the lane masks and the edge's terms
+// of the merit function; each endpoint stores the Jacobian scalars at its own
+// incidence position.
+
+template <int NPER>
+struct EdgeGradUnroll {
+    static constexpr int U = NPER <= 2 ? 4 : NPER == 4 ? 2 : 1;
+};
+
+template <int LPR, int NPER, int Q>
+__global__ __launch_bounds__(kBlock) void k_edge_grad_win(DevGraph g, int d, ScatterOut so,
+                                                          double gamma,
+                                                          const double* __restrict__ U,
+                                                          double* __restrict__ Pi, Payload pl,
+                                                          double* __restrict__ epart,
+                                                          double* __restrict__ spart) {
+    constexpr int UB = EdgeGradUnroll<NPER>::U;
+    constexpr int NM = meta_slots<LPR, NPER>();
+    constexpr bool PF = NM <= 4;
+    constexpr int GPB = kBlock / LPR;
+    __shared__ double piece[GPB][2][NPER][LPR];
+    __shared__ int head_v[GPB];
+    const int lane = threadIdx.x & 63;
+    const int gl = lane % LPR;
+    const int rg = threadIdx.x / LPR;
+    const double sigma = so.sigma;
+    double acc4[kScatterNV] = {0.0, 0.0, 0.0, 0.0};
+    double eacc[kEdgeSsnalNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int w = blockIdx.x; w < int(g.nwin); w += gridDim.x) {
+        const GroupRange gr = group_range(g, w, rg, GPB);
+        int vcur = -1;
+        bool first = true;
+        int head = -1;
+        double acc[NPER], dg[NPER], xr[NPER], ar[NPER];
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = xr[t] = ar[t] = 0.0;
+        auto finish = [&]() { scatter_finish<LPR, NPER, true>(vcur, d, gl, so, xr, ar, acc, dg, acc4); };
+        auto done = [&](bool cut_start) {
+            if (!cut_start) {
+                finish();
+            } else {
+#pragma unroll
+                for (int t = 0; t < NPER; ++t) {
+                    piece[rg][0][t][gl] = acc[t];
+                    piece[rg][1][t][gl] = dg[t];
+                }
+                head = vcur;
+            }
+        };
+        constexpr int CP = NM * LPR;
+        for (int pc = gr.p0, pe = 0; pc < gr.p1; pc = pe) {
+            pe = (PF && gr.p1 - pc > CP) ? pc + CP : gr.p1;
+            ChunkMeta<LPR, PF ? NM : 1> cm;
+            if constexpr (PF) chunk_meta_load<LPR, NM, Q, false>(g, pc, pe, gl, pl, cm);
+            for (int p0 = pc; p0 < pe; p0 += UB) {
+                Meta mt[UB];
+#pragma unroll
+                for (int u = 0; u < UB; ++u)
+                    if (p0 + u < pe) {
+                        if constexpr (PF)
+                            mt[u] = chunk_meta_get<LPR, NM, Q, false, false>(cm, p0 + u - pc);
+                        else
+                            mt[u] = load_meta<Q, false>(g, p0 + u, pl);
+                    }
+                double xo[UB][NPER], ur[UB][NPER], wl[UB];
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    const bool ok = p0 + u < pe;
+                    wl[u] = ok ? g.w[mt[u].l] : 0.0;
+#pragma unroll
+                    for (int t = 0; t < NPER; ++t) {
+                        const int k = gl + LPR * t;
+                        xo[u][t] = (ok && k < d) ? so.X[int64_t(mt[u].o) * d + k] : 0.0;
+                        ur[u][t] = (ok && k < d) ? U[int64_t(mt[u].l) * d + k] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    if (p0 + u >= pe) break;
+                    const Meta& m = mt[u];
+                    if (m.v != vcur) {
+                        if (vcur >= 0) {
+                            done(first && vcur == gr.vprev);
+                            first = false;
+                        }
+                        vcur = m.v;
+                        load_row<LPR, NPER>(so.X, vcur, d, gl, xr);
+                        load_row<LPR, NPER>(so.A, vcur, d, gl, ar);
+#pragma unroll
+                        for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = 0.0;
+                    }
+                    // the edge's row, oriented first endpoint minus second
+                    const double r = gamma * wl[u];
+                    double bx[NPER], y[NPER];
+#pragma unroll
+                    for (int t = 0; t < NPER; ++t) {
+                        bx[t] = m.pos ? xr[t] - xo[u][t] : xo[u][t] - xr[t];
+                        y[t] = ur[u][t] + sigma * bx[t];
+                    }
+                    RowProj<LPR, NPER, Q> o;
+                    project_row<LPR, NPER, Q, true>(y, gl, lane, d, r, o);
+#pragma unroll
+                    for (int t = 0; t < NPER; ++t) acc[t] += m.pos ? o.pi[t] : -o.pi[t];
+                    if constexpr (Q == kQ2) {
+                        const double ir = 1.0 / r;
+                        if (o.alpha >= 1.0) {
+#pragma unroll
+                            for (int t = 0; t < NPER; ++t) dg[t] += 1.0;
+                        } else if (o.alpha > 0.0) {
+#pragma unroll
+                            for (int t = 0; t < NPER; ++t) {
+                                const double yh = o.pi[t] * ir;
+                                dg[t] += o.alpha * (1.0 - yh * yh);
+                            }
+                        }
+                        if (gl == 0) pl.ipay[p0 + u] = double2{o.alpha, ir};
+                    } else if constexpr (Q == kQ1) {
+#pragma unroll
+                        for (int t = 0; t < NPER; ++t)
+                            if ((o.lm >> t) & 1u) dg[t] += 1.0;
+                    } else {
+                        if (o.cnt < 0) {
+#pragma unroll
+                            for (int t = 0; t < NPER; ++t) dg[t] += 1.0;
+                        } else if (o.cnt > 0) {
+                            const double f = 1.0 - 1.0 / double(o.cnt);
+#pragma unroll
+                            for (int t = 0; t < NPER; ++t)
+                                if ((o.lm >> t) & 1u) dg[t] += f;
+                        }
+                        if (gl == 0) pl.ipay[p0 + u] = double2{double(o.cnt), 0.0};
+                    }
+                    if (m.pos) {
+                        const int64_t l = m.l;
+#pragma unroll
+                        for (int t = 0; t < NPER; ++t) {
+                            const int k = gl + LPR * t;
+                            if (k < d) {
+                                Pi[l * d + k] = o.pi[t];
+                                const double e = o.pi[t] - ur[u][t];
+                                eacc[0] += bx[t] * o.pi[t];
+                                eacc[1] += e * e;
+                                eacc[2] += bx[t] * bx[t];
+                                eacc[3] += o.pi[t] * o.pi[t];
+                            }
+                        }
+                        if constexpr (Q != kQ2) pl.lbits[l * LPR + gl] = o.lm;
+                        if (gl == 0) {
+                            if constexpr (Q == kQ2) eacc[4] += (o.alpha < 1.0) ? 1.0 : 0.0;
+                            else if constexpr (Q == kQInf) eacc[4] += (o.cnt >= 0) ? 1.0 : 0.0;
+                            else eacc[4] += 1.0;
+                        }
+                    }
+                }
+            }
+        }
+        bool pend = false;
+        if (vcur >= 0) {
+            const bool cs = first && vcur == gr.vprev;
+            if (!cs && vcur == gr.vnext) pend = true;
+            else done(cs);
+        }
+        if (gl == 0) head_v[rg] = head;
+        __syncthreads();
+        if (pend) {
+            for (int j = rg + 1; j < GPB && head_v[j] == vcur; ++j) {
+#pragma unroll
+                for (int t = 0; t < NPER; ++t) {
+                    acc[t] += piece[j][0][t][gl];
+                    dg[t] += piece[j][1][t][gl];
+                }
+            }
+            finish();
+        }
+        __syncthreads();
+    }
+    // isolated vertices
+    for (int64_t i = int64_t(blockIdx.x) * GPB + rg; i < g.niso; i += int64_t(gridDim.x) * GPB) {
+        const int64_t v = g.iso[i];
+        double acc[NPER], dg[NPER], xr[NPER], ar[NPER];
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = 0.0;
+        load_row<LPR, NPER>(so.X, v, d, gl, xr);
+        load_row<LPR, NPER>(so.A, v, d, gl, ar);
+        scatter_finish<LPR, NPER, true>(v, d, gl, so, xr, ar, acc, dg, acc4);
+    }
+    block_reduce_store<kScatterNV>(acc4, spart + blockIdx.x * kScatterNV);
+    block_reduce_store<kEdgeSsnalNV>(eacc, epart + blockIdx.x * kEdgeSsnalNV);
+}
+
 // ---- Newton matvec ------------------------------------------------------------
 
 struct MatvecOut {
@@ -654,6 +850,25 @@ int launch_scatter(const DevGraph& g, int d, int qk, double cx, const double* X,
                                    s, g, d, so, Z, pl, partials);
             });
         }
+        total = g1;
+    });
+    return total;
+}
+
+int launch_edge_grad(const DevGraph& g, int d, int qk, double gamma, double sigma,
+                     const double* X, const double* U, const double* A, double* Pi, Payload pl,
+                     double* G, double* Dinv, double* epart, double* spart, hipStream_t s) {
+    int total = 0;
+    ScatterOut so{1.0, -1.0, 1.0, sigma, X, A, G, Dinv, nullptr};
+    dispatch_row(d, [&](auto L, auto N) {
+        constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
+        const int g1 = window_grid<lpr>(g);
+        if (qk == kQ1)
+            hipLaunchKernelGGL((k_edge_grad_win<lpr, nper, kQ1>), dim3(g1), dim3(kBlock), 0, s, g,
+                               d, so, gamma, U, Pi, pl, epart, spart);
+        else
+            hipLaunchKernelGGL((k_edge_grad_win<lpr, nper, kQ2>), dim3(g1), dim3(kBlock), 0, s, g,
+                               d, so, gamma, U, Pi, pl, epart, spart);
         total = g1;
     });
     return total;
