@@ -223,3 +223,40 @@ def test_knn_u8_rejects_bad_arguments():
         ccm.ccm_build_knn_graph_u8(K, 1.0, 3)
     with pytest.raises(ccm.CcmError):
         ccm.ccm_build_knn_graph_u8(K[:, :5].contiguous(), 0.0, 3)
+
+
+def _big_hub_graph(n, seed, hub_deg):
+    """Random sparse graph plus vertex 5 joined to hub_deg others.  For rows of
+    d >= 33 values a window holds at most 256 incidences, so the hub's list
+    is split over every row group of its workgroup and over several rounds
+    of loads; for d = 3 it sits inside one large window."""
+    rng = np.random.default_rng(seed)
+    src, dst, w = synthdata.random_graph(n, 3 * n, seed)
+    keys = {(int(a), int(b)): float(c) for a, b, c in zip(src, dst, w)}
+    for j in rng.choice(np.arange(6, n), hub_deg, replace=False):
+        keys.setdefault((5, int(j)), float(rng.uniform(0.1, 1.0)))
+    e = sorted(keys)
+    return (np.array([a for a, _ in e], np.int32), np.array([b for _, b in e], np.int32),
+            np.array([keys[k] for k in e]))
+
+
+@pytest.mark.parametrize("d", [3, 64, 130, 784])
+def test_scatter_and_matvec_with_a_hub_longer_than_a_window(d):
+    torch, ccm = need_gpu()
+    rng = np.random.default_rng(1100 + d)
+    n = 900
+    src, dst, w = _big_hub_graph(n, 40 + d, 600)
+    assert np.bincount(np.r_[src, dst], minlength=n).max() >= 600
+    B = oracle.incidence(src, dst, n)
+    Z = rng.normal(size=(len(src), d))
+    out = host(ccm.ccm_op_scatter(dev(Z), dev(src), dev(dst), n))
+    assert np.allclose(out, B.T @ Z, rtol=1e-13, atol=1e-12)
+    for q in QS:
+        X = rng.normal(size=(n, d))
+        U = rng.normal(size=(len(src), d)) * 0.3
+        V = rng.normal(size=(n, d))
+        g, sig = 0.8, 2.5
+        res, _ = ccm.ccm_op_hess_matvec(dev(X), dev(U), *graph_dev(src, dst, w), g, sig, q, dev(V))
+        Y = U + sig * (B @ X)
+        ref = V + sig * (B.T @ ops.jacobian_apply(Y, g * w, q, B @ V))
+        assert rel(host(res), ref) <= 1e-12, q

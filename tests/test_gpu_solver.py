@@ -310,6 +310,25 @@ def test_batched_matches_single_instance_solves():
                 assert res[k]["n_clusters"][t] == ref["n_clusters"][t]
 
 
+@pytest.mark.parametrize("q", QS)
+def test_path_with_a_hub_longer_than_a_window(q):
+    # the fused edge pass + gradient (q = 1, 2) and the scatter (q = inf) on a
+    # graph whose hub has more incidences than a window holds
+    rng = np.random.default_rng(1200)
+    n, d = 700, 40  # rows of 40 values: windows of at most 256 incidences
+    A = rng.normal(size=(n, d))
+    src, dst, w, *_ = oracle.knn_graph(A, 5, None)
+    keys = {(int(a), int(b)): float(c) for a, b, c in zip(src, dst, w)}
+    for j in rng.choice(np.arange(1, n), 400, replace=False):
+        keys.setdefault((0, int(j)), float(rng.uniform(0.05, 0.3)))
+    e = sorted(keys)
+    src = np.array([a for a, _ in e], np.int32)
+    dst = np.array([b for _, b in e], np.int32)
+    w = np.array([keys[k] for k in e])
+    assert np.bincount(np.r_[src, dst], minlength=n).max() >= 400
+    _compare_path(A, src, dst, w, [0.01, 0.05], q, "ssnal", 1e-7, x_tol=1e-5)
+
+
 def test_batched_groups_concurrent_and_reproducible():
     # the (q, d) groups run at once on streams of their own: results are the
     # same run to run and when the call is made on a side stream whose own
