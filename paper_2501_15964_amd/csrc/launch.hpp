@@ -180,11 +180,13 @@ constexpr int kMatvecNV = 1;
 // or 2, any other qk is taken as 2): Pi =
 // Pi_C(U + sigma B X) and its Jacobian payload as launch_edge_ssnal, G = X -
 // A + B^T Pi and Dinv as launch_scatter(diag); edge partials (kEdgeSsnalNV)
-// to epart and vertex partials (kScatterNV) to spart, one row per block.
-// Returns the number of blocks.
+// to epart and vertex partials (kScatterNV) to spart, one row per block;
+// with kpart, also the KKT edge terms at (X, U) as launch_edge_kkt (kEdgeKktNV
+// per block).  Returns the number of blocks.
 int launch_edge_grad(const DevGraph& g, int d, int qk, double gamma, double sigma,
                      const double* X, const double* U, const double* A, double* Pi, Payload pl,
-                     double* G, double* Dinv, double* epart, double* spart, hipStream_t s);
+                     double* G, double* Dinv, double* epart, double* spart, hipStream_t s,
+                     double* kpart = nullptr);
 int launch_matvec(const DevGraph& g, int d, int qk, int mode, const double* V, const double* Pi,
                   Payload pl, double gamma, double sigma, double c0, const double* dscale,
                   double* out, double* partials, CgSkip skip, hipStream_t s);

@@ -732,13 +732,29 @@ struct Solver::Impl {
             // KKT at (X, U): R_D from the last gradient, the rest from one pass;
             // the next outer iteration's edge pass and gradient are enqueued
             // with it (discarded if this one converges)
-            {
-                Timed t(prof, CCM_K_EDGE);
-                const int gp = launch_edge_kkt(g, d, qk, gamma, X, U, nullptr, pk.as<double>(), s);
-                defer_finalize(pk.as<double>(), gp, kEdgeKktNV, slot(kK), s);
-            }
             const bool next = k + 1 < o.max_outer;
-            if (next) edge_grad(X, Pi, pl, gamma, G, Dinv, pe.as<double>(), ps.as<double>(), kE, kS);
+            // Rows of more than 256 values: one launch, the KKT terms from the
+            // next pass's edge rows (saves reading X and U again; at these
+            // widths the kernel runs at its lowest occupancy either way, while
+            // for shorter rows the extra terms cost occupancy and time)
+            if (next && qk != kQInf && d > 256) {
+                Timed t(prof, CCM_K_EDGE);
+                const int gp = launch_edge_grad(g, d, qk, gamma, sigma, X, U, A, Pi, pl, G, Dinv,
+                                                pe.as<double>(), ps.as<double>(), s,
+                                                pk.as<double>());
+                defer_finalize(pe.as<double>(), gp, kEdgeSsnalNV, slot(kE), s);
+                defer_finalize(ps.as<double>(), gp, kScatterNV, slot(kS), s);
+                defer_finalize(pk.as<double>(), gp, kEdgeKktNV, slot(kK), s);
+            } else {
+                {
+                    Timed t(prof, CCM_K_EDGE);
+                    const int gp =
+                        launch_edge_kkt(g, d, qk, gamma, X, U, nullptr, pk.as<double>(), s);
+                    defer_finalize(pk.as<double>(), gp, kEdgeKktNV, slot(kK), s);
+                }
+                if (next)
+                    edge_grad(X, Pi, pl, gamma, G, Dinv, pe.as<double>(), ps.as<double>(), kE, kS);
+            }
             CHK(read(next ? kE : kK, kK + kEdgeKktNV));
             kkt_from(ev, res);
             if (!std::isfinite(res[6])) {

@@ -403,13 +403,17 @@ struct EdgeGradUnroll {
     static constexpr int U = NPER <= 2 ? 4 : NPER == 4 ? 2 : 1;
 };
 
-template <int LPR, int NPER, int Q>
+// With KKT, the first endpoint also adds the edge's terms of the KKT
+// residuals at (X, U) (as k_edge_kkt: ||Pi_C(BX + U) - U||^2, ||BX||^2,
+// ||U||^2, ||U - Pi_C(U)||^2, r ||(BX)_l||_q) into kpart.
+template <int LPR, int NPER, int Q, bool KKT>
 __global__ __launch_bounds__(kBlock) void k_edge_grad_win(DevGraph g, int d, ScatterOut so,
                                                           double gamma,
                                                           const double* __restrict__ U,
                                                           double* __restrict__ Pi, Payload pl,
                                                           double* __restrict__ epart,
-                                                          double* __restrict__ spart) {
+                                                          double* __restrict__ spart,
+                                                          double* __restrict__ kpart) {
     constexpr int UB = EdgeGradUnroll<NPER>::U;
     constexpr int NM = meta_slots<LPR, NPER>();
     constexpr bool PF = NM <= 4;
@@ -422,6 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_grad_win(DevGraph g, int d, Sca
     const double sigma = so.sigma;
     double acc4[kScatterNV] = {0.0, 0.0, 0.0, 0.0};
     double eacc[kEdgeSsnalNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double kacc[kEdgeKktNV] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int w = blockIdx.x; w < int(g.nwin); w += gridDim.x) {
         const GroupRange gr = group_range(g, w, rg, GPB);
         int vcur = -1;
@@ -546,6 +551,34 @@ __global__ __launch_bounds__(kBlock) void k_edge_grad_win(DevGraph g, int d, Sca
                             else if constexpr (Q == kQInf) eacc[4] += (o.cnt >= 0) ? 1.0 : 0.0;
                             else eacc[4] += 1.0;
                         }
+                        if constexpr (KKT) {
+                            double v[NPER], nq = 0.0;
+#pragma unroll
+                            for (int t = 0; t < NPER; ++t) {
+                                v[t] = bx[t] + ur[u][t];
+                                if constexpr (Q == kQ1) nq += fabs(bx[t]);
+                                else nq += bx[t] * bx[t];
+                            }
+                            double pen;
+                            if constexpr (Q == kQ2) pen = r * sqrt(group_sum<LPR>(nq));
+                            else pen = group_sum<LPR>(r * nq);
+                            if (gl == 0) kacc[4] += pen;
+                            RowProj<LPR, NPER, Q> pv, pu;
+                            project_row<LPR, NPER, Q, false>(v, gl, lane, d, r, pv);
+                            project_row<LPR, NPER, Q, false>(ur[u], gl, lane, d, r, pu);
+#pragma unroll
+                            for (int t = 0; t < NPER; ++t) {
+                                const int k = gl + LPR * t;
+                                if (k < d) {
+                                    const double e = pv.pi[t] - ur[u][t];
+                                    const double f = ur[u][t] - pu.pi[t];
+                                    kacc[0] += e * e;
+                                    kacc[1] += bx[t] * bx[t];
+                                    kacc[2] += ur[u][t] * ur[u][t];
+                                    kacc[3] += f * f;
+                                }
+                            }
+                        }
                     }
                 }
             }
@@ -582,6 +615,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_grad_win(DevGraph g, int d, Sca
     }
     block_reduce_store<kScatterNV>(acc4, spart + blockIdx.x * kScatterNV);
     block_reduce_store<kEdgeSsnalNV>(eacc, epart + blockIdx.x * kEdgeSsnalNV);
+    if constexpr (KKT) block_reduce_store<kEdgeKktNV>(kacc, kpart + blockIdx.x * kEdgeKktNV);
 }
 
 // ---- Newton matvec ------------------------------------------------------------
@@ -857,18 +891,26 @@ int launch_scatter(const DevGraph& g, int d, int qk, double cx, const double* X,
 
 int launch_edge_grad(const DevGraph& g, int d, int qk, double gamma, double sigma,
                      const double* X, const double* U, const double* A, double* Pi, Payload pl,
-                     double* G, double* Dinv, double* epart, double* spart, hipStream_t s) {
+                     double* G, double* Dinv, double* epart, double* spart, hipStream_t s,
+                     double* kpart) {
     int total = 0;
     ScatterOut so{1.0, -1.0, 1.0, sigma, X, A, G, Dinv, nullptr};
     dispatch_row(d, [&](auto L, auto N) {
         constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
         const int g1 = window_grid<lpr>(g);
-        if (qk == kQ1)
-            hipLaunchKernelGGL((k_edge_grad_win<lpr, nper, kQ1>), dim3(g1), dim3(kBlock), 0, s, g,
-                               d, so, gamma, U, Pi, pl, epart, spart);
-        else
-            hipLaunchKernelGGL((k_edge_grad_win<lpr, nper, kQ2>), dim3(g1), dim3(kBlock), 0, s, g,
-                               d, so, gamma, U, Pi, pl, epart, spart);
+        auto go = [&](auto Qc, auto Kc) {
+            constexpr int q = decltype(Qc)::value;
+            constexpr bool kkt = decltype(Kc)::value != 0;
+            hipLaunchKernelGGL((k_edge_grad_win<lpr, nper, q, kkt>), dim3(g1), dim3(kBlock), 0, s,
+                               g, d, so, gamma, U, Pi, pl, epart, spart, kpart);
+        };
+        if (qk == kQ1) {
+            if (kpart) go(IC<kQ1>{}, IC<1>{});
+            else go(IC<kQ1>{}, IC<0>{});
+        } else {
+            if (kpart) go(IC<kQ2>{}, IC<1>{});
+            else go(IC<kQ2>{}, IC<0>{});
+        }
         total = g1;
     });
     return total;

@@ -329,6 +329,18 @@ def test_path_with_a_hub_longer_than_a_window(q):
     _compare_path(A, src, dst, w, [0.01, 0.05], q, "ssnal", 1e-7, x_tol=1e-5)
 
 
+@pytest.mark.parametrize("q", QS)
+def test_path_long_rows(q):
+    # rows of 300 values: for q = 1, 2 the KKT terms come from the fused
+    # edge pass of the next outer iteration (one launch)
+    rng = np.random.default_rng(1300)
+    n, d = 180, 300
+    centres = rng.normal(size=(3, d)) * 2.0
+    A = centres[rng.integers(0, 3, size=n)] + rng.normal(size=(n, d))
+    src, dst, w, *_ = oracle.knn_graph(A, 6, None)
+    _compare_path(A, src, dst, w, [0.02, 0.2, 2.0], q, "ssnal", 1e-7, x_tol=1e-5)
+
+
 def test_batched_groups_concurrent_and_reproducible():
     # the (q, d) groups run at once on streams of their own: results are the
     # same run to run and when the call is made on a side stream whose own
