@@ -105,6 +105,12 @@ struct Prof {
         const size_t loc = size_t(id) - base;
         if (loc < used / 2) cls[loc] = c;
     }
+    // algorithmic bytes of a recorded launch, known only after it was issued
+    void set_bytes(int64_t id, double b) {
+        if (!on || id < int64_t(base)) return;
+        const size_t loc = size_t(id) - base;
+        if (loc < used / 2) pbytes[loc] = b;
+    }
     // accumulate the pairs with id < id_end (their events have completed)
     void harvest_until(int64_t id_end) {
         if (!on) return;
@@ -313,11 +319,33 @@ struct Solver::Impl {
     ccm_status read(int a, int b, bool harvest = true) {
         (void)a;
         (void)b;
+        CHK(read_begin());
+        return read_wait(harvest);
+    }
+    // The same in two halves: work enqueued between them runs on the device
+    // while the host waits for, and then acts on, the values.
+    int64_t read_pid = 0;
+    ccm_status read_begin() {
         flush_finalize();
         HIPCHK(hipEventRecord(sync_ev, s));
-        CHK(spin(sync_ev));
-        if (harvest) prof.harvest();
+        read_pid = prof.next_pair();
         return CCM_OK;
+    }
+    ccm_status read_wait(bool harvest = true) {
+        CHK(spin(sync_ev));
+        if (harvest) prof.harvest_until(read_pid);
+        return CCM_OK;
+    }
+    // The next Newton step's CG start (x = 0, r = -G, the first matvec) needs
+    // nothing the host decides, so it is enqueued right after a read that
+    // opens an outer iteration; the host fills in the CG threshold before the
+    // first update.  Unused if the iteration takes no Newton step.
+    bool cg_pre = false;
+    int64_t cg_pre_pair = -1;
+    void cg_prestart(double gamma) {
+        cg_begin(0, G, true, Dinv, 0.0, gamma, Pi, pl);
+        cg_pre_pair = prof.last_pair();
+        cg_pre = true;
     }
     double* slot(int k) { return dslot + k; }
 
@@ -635,7 +663,9 @@ struct Solver::Impl {
         // values of the first outer iteration's merit function; later ones are
         // enqueued with the KKT pass of the iteration before
         edge_grad(X, Pi, pl, gamma, G, Dinv, pe.as<double>(), ps.as<double>(), kE, kS);
-        CHK(read(kE, kS + kScatterNV));
+        CHK(read_begin());
+        cg_prestart(gamma);
+        CHK(read_wait());
         Ev ev = make_ev(kE, kS);
         for (int k = 0; k < o.max_outer; ++k) {
             st.outer++;
@@ -658,7 +688,14 @@ struct Solver::Impl {
                 const double rtol = std::min(0.1, std::pow(ev.gn, 0.2));
                 const double thr = rtol * rtol * ev.G2;
                 int iters = 0;
-                cg_begin(0, G, true, Dinv, thr, gamma, Pi, pl);
+                if (cg_pre) {
+                    cr.thr = thr;
+                    cr.mv_bytes = last_bytes;
+                    prof.set_bytes(cg_pre_pair, last_bytes);
+                    cg_pre = false;
+                } else {
+                    cg_begin(0, G, true, Dinv, thr, gamma, Pi, pl);
+                }
                 CHK(cg_issue(cr.P[0], cg_first(0) + 1));
                 trial_eval(1.0, gamma);
                 CHK(read(kT, kST + kScatterNV, false));
@@ -715,6 +752,7 @@ struct Solver::Impl {
                 std::swap(Dinv, Dinvt);
                 ev = evt;
                 last_bytes = matvec_bytes(ev.nout);
+                cg_pre = false;
             }
             if (numerical) break;
             // multiplier update U <- Pi_C(U + sigma B X), already in Pi
@@ -755,7 +793,9 @@ struct Solver::Impl {
                 if (next)
                     edge_grad(X, Pi, pl, gamma, G, Dinv, pe.as<double>(), ps.as<double>(), kE, kS);
             }
-            CHK(read(next ? kE : kK, kK + kEdgeKktNV));
+            CHK(read_begin());
+            if (next) cg_prestart(gamma);
+            CHK(read_wait());
             kkt_from(ev, res);
             if (!std::isfinite(res[6])) {
                 numerical = true;
