@@ -681,7 +681,8 @@ struct Solver::Impl {
                     return CCM_OK;
                 }
                 // Newton direction: (I + sigma B^T P B) D = -G.  The first
-                // chunk of CG iterations (one more than the last solve took)
+                // chunk of CG iterations (three more than the last solve took:
+                // a launch returning at once costs far less than a miss)
                 // and the full-step trial are enqueued together; the trial's
                 // read also brings the CG status, and only if the CG needs more
                 // iterations is it continued and the trial redone.
@@ -696,7 +697,7 @@ struct Solver::Impl {
                 } else {
                     cg_begin(0, G, true, Dinv, thr, gamma, Pi, pl);
                 }
-                CHK(cg_issue(cr.P[0], cg_first(0) + 1));
+                CHK(cg_issue(cr.P[0], cg_first(0) + 2));
                 trial_eval(1.0, gamma);
                 CHK(read(kT, kST + kScatterNV, false));
                 if (cr.P[0].hf[0]) {
