@@ -310,10 +310,12 @@ def test_batched_matches_single_instance_solves():
                 assert res[k]["n_clusters"][t] == ref["n_clusters"][t]
 
 
-@pytest.mark.parametrize("q", QS)
-def test_path_with_a_hub_longer_than_a_window(q):
-    # the fused edge pass + gradient (q = 1, 2) and the scatter (q = inf) on a
-    # graph whose hub has more incidences than a window holds
+@pytest.mark.parametrize("q,method", [(1.0, "ssnal"), (2.0, "ssnal"), (np.inf, "ssnal"),
+                                      (2.0, "admm")])
+def test_path_with_a_hub_longer_than_a_window(q, method):
+    # the fused edge pass + gradient (q = 1, 2), the scatter (q = inf) and the
+    # Laplacian matvec of ADMM on a graph whose hub has more incidences than a
+    # window holds
     rng = np.random.default_rng(1200)
     n, d = 700, 40  # rows of 40 values: windows of at most 256 incidences
     A = rng.normal(size=(n, d))
@@ -326,7 +328,7 @@ def test_path_with_a_hub_longer_than_a_window(q):
     dst = np.array([b for _, b in e], np.int32)
     w = np.array([keys[k] for k in e])
     assert np.bincount(np.r_[src, dst], minlength=n).max() >= 400
-    _compare_path(A, src, dst, w, [0.01, 0.05], q, "ssnal", 1e-7, x_tol=1e-5)
+    _compare_path(A, src, dst, w, [0.01, 0.05], q, method, 1e-7, x_tol=1e-5)
 
 
 @pytest.mark.parametrize("q", QS)
