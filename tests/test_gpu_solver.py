@@ -217,6 +217,30 @@ def test_vjp_matches_oracle_gradient():
     assert abs(dg - rg) <= 1e-6 * (1 + abs(rg))
 
 
+def test_vjp_clusters_larger_than_a_window():
+    # four clusters of 320 points at d = 40: each cluster's membership list
+    # is longer than a window (256 entries), so the cluster sums of the
+    # adjoint go through the split-window path
+    torch, ccm = need_gpu()
+    A, _, T = synthdata.mixture32(seed=1007, n_per=320, d=40, n_blobs=4)
+    A = A / 3.0
+    src, dst, w, *_ = oracle.knn_graph(A, 5, None)
+    n = A.shape[0]
+    g = 8.0
+    Xo, Uo, _, _ = oracle.ssnal(A, src, dst, w, g, 2.0, 1e-12)
+    lab, K = oracle.cluster_labels(Xo, src, dst, n, oracle.fusion_scale(A))
+    assert K == 4 and np.bincount(lab).min() > 256
+    out = ccm.ccm_solve_path(dev(A), *graph_dev(src, dst, w), [g], 2.0, 1e-11)
+    X = out["X"][0]
+    assert np.array_equal(host(out["labels"][0]), lab)
+    dA, dlw, dg, _ = ccm.ccm_path_vjp(dev(A), *graph_dev(src, dst, w), g, X, out["labels"][0],
+                                      dev(2 * (host(X) - T)), tol=1e-13)
+    rA, rlw, rg = oracle.path_vjp(A, src, dst, w, g, Xo, 2 * (Xo - T), labels=lab)
+    assert rel(host(dA), rA) <= 1e-6
+    assert rel(host(dlw), rlw) <= 1e-6
+    assert abs(dg - rg) <= 1e-6 * (1 + abs(rg))
+
+
 def test_vjp_central_differences_on_gpu():
     torch, ccm = need_gpu()
     A, src, dst, w, T = _adjoint_problem(n_per=30, d=3, seed=77)
