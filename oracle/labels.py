@@ -18,7 +18,11 @@ max(s_l, t_l) with s_l the scaled gap above and t_l = 1 - ||u_l||_{q*}/r_l
 the dual slack; a gamma is label-eligible when every margin exceeds 1e-4.
 
 Parity: pinned by the two-point closed form (fused iff 2 gamma w >=
-||a_1 - a_2||_q) and by the full-fusion certificate in the tests.
+||a_1 - a_2||_{q*}) and by the full-fusion certificate; the numbering by a
+hand-built graph with its label vector written out; the margins by the
+two-point primal and dual solutions in closed form (primal gap below the
+fusion threshold, dual slack above it, the dual norm where it differs from
+the q-norm).
 """
 from __future__ import annotations
 
