@@ -218,6 +218,8 @@ def main():
     ap.add_argument("--batched-count", type=int, default=512)
     ap.add_argument("--batched-budget", type=float, default=90.0,
                     help="wall-clock budget (s) of each (q, d) group of the batched leg")
+    ap.add_argument("--locality", type=int, default=-1, choices=(-1, 0, 1),
+                    help="vertex processing order of the library (-1: its default)")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without HIP events around the matvec launches (roofline then "
                          "omitted)")
@@ -242,8 +244,8 @@ def main():
     # timed steps: HIP events around the Newton/CG matvec launches only (profile
     # level 2), which the roofline figure needs; one extra untimed step with
     # every kernel class timed (level 1) gives the per-class breakdown
-    opts = ccm.ccm_default_options(profile=0 if args.no_profile else 2)
-    opts_all = ccm.ccm_default_options(profile=1)
+    opts = ccm.ccm_default_options(profile=0 if args.no_profile else 2, locality=args.locality)
+    opts_all = ccm.ccm_default_options(profile=1, locality=args.locality)
 
     def step(o=opts):
         t0 = time.perf_counter()

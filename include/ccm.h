@@ -93,6 +93,13 @@ typedef struct {
     double sigma_max;      /* SSNAL penalty cap.  1e4 */
     double tau;            /* ADMM multiplier step.  1.618 */
     double time_budget_s;  /* wall-clock budget for the whole path; <= 0: none */
+    int32_t locality;      /* order in which the vertex kernels visit the points:
+                              1: connected components one after another, each in
+                              breadth-first levels from its smallest point (the
+                              rows gathered at the same time are neighbours, so
+                              the caches hold them); 0: the input order; -1
+                              (default): 1 when n d >= 2^22, else 0.  Changes the
+                              summation order only, never the data layout */
 } ccm_options;
 
 ccm_options ccm_default_options(void);

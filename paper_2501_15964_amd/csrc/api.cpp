@@ -78,6 +78,7 @@ ccm_options defaults() {
     o.sigma_max = 1e4;
     o.tau = 1.618;
     o.time_budget_s = 0.0;
+    o.locality = -1;
     return o;
 }
 
@@ -153,7 +154,7 @@ ccm_status solve_group(const ccm_instance* inst_host, const std::vector<int>& id
     std::string err;
     OwnedGraph og;
     st = graph_build(su.as<int>(), du.as<int>(), wu.as<double>(), mU, nU, d, true, stream, og,
-                     err);
+                     err, o.locality);
     if (st != CCM_OK) return fail(st, err);
     Solver solver(og.g, d, qk, Au.as<double>(), stream, o, tol, err);
     st = solver.run_batched(gammas_host, n_gamma, b);
@@ -286,7 +287,7 @@ ccm_status ccm_solve_path(const double* A, int64_t n, int64_t d, const int32_t* 
     if (n_gamma == 0) return CCM_OK;
     std::string err;
     OwnedGraph og;
-    st = graph_build(src, dst, w, m, n, int(d), false, stream, og, err);
+    st = graph_build(src, dst, w, m, n, int(d), false, stream, og, err, o.locality);
     if (st != CCM_OK) return fail(st, err);
     Solver solver(og.g, int(d), qk, A, stream, o, tol, err);
     st = solver.run_path(gammas_host, n_gamma, X_warm, U_warm, X_out, U_out, labels_out,
@@ -500,7 +501,7 @@ ccm_status ccm_op_scatter(const double* Z, int64_t m, int64_t d, const int32_t* 
     st = graph_build(src, dst, wbuf.as<double>(), m, n, int(d), true, stream, og, err);
     if (st != CCM_OK) return fail(st, err);
     DevMem part;
-    HIPCHK_API(part.alloc(size_t(kPartialsCap) * 8, stream));
+    HIPCHK_API(part.alloc(partials_for(og.g) * 8, stream));
     launch_scatter(og.g, int(d), kQ2, 0.0, nullptr, 0.0, nullptr, 1.0, Z, out, false, Payload{},
                    0.0, 0.0, nullptr, part.as<double>(), stream);
     HIPCHK_API(hipGetLastError());
@@ -528,7 +529,7 @@ ccm_status ccm_op_hess_matvec(const double* X, const double* U, int64_t n, int64
     HIPCHK_API(Pi.alloc(size_t(std::max<int64_t>(M, 1)) * 8, stream));
     HIPCHK_API(ip.alloc(size_t(std::max<int64_t>(og.g.nent, 1)) * 16, stream));
     HIPCHK_API(lb.alloc(size_t(std::max<int64_t>(m, 1)) * lbits_per_edge(int(d)) * 4, stream));
-    HIPCHK_API(part.alloc(size_t(kPartialsCap) * 8, stream));
+    HIPCHK_API(part.alloc(partials_for(og.g) * 8, stream));
     Payload pl{ip.as<double2>(), lb.as<uint32_t>()};
     if (m > 0)
         launch_edge_ssnal(og.g, int(d), qk, gamma, sigma, X, U, Pi.as<double>(), pl,
@@ -569,9 +570,9 @@ ccm_status ccm_kkt(const double* A, const double* X, const double* U, int64_t n,
     DevMem Uf, G, p1, p2, p3, sc;
     HIPCHK_API(Uf.alloc(size_t(M) * 8, stream));
     HIPCHK_API(G.alloc(size_t(N) * 8, stream));
-    HIPCHK_API(p1.alloc(size_t(kPartialsCap) * 8, stream));
-    HIPCHK_API(p2.alloc(size_t(kPartialsCap) * 8, stream));
-    HIPCHK_API(p3.alloc(size_t(kPartialsCap) * 8, stream));
+    HIPCHK_API(p1.alloc(partials_for(og.g) * 8, stream));
+    HIPCHK_API(p2.alloc(partials_for(og.g) * 8, stream));
+    HIPCHK_API(p3.alloc(partials_for(og.g) * 8, stream));
     HIPCHK_API(sc.alloc(32 * 8, stream));
     double* s = sc.as<double>();
     // KKT edge pass on (X, U), writing Pi_C(U) for the dual objective

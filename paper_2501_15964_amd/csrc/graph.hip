@@ -114,6 +114,95 @@ __global__ __launch_bounds__(kBlock) void k_epos(int64_t cnt, const Inc* __restr
     }
 }
 
+// ---- locality order ---------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int64_t n, int v, int* __restrict__ x) {
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * kBlock)
+        x[i] = v;
+}
+
+// first[c] = smallest vertex of component c (first preset to INT_MAX)
+__global__ __launch_bounds__(kBlock) void k_comp_first(int64_t n, const int* __restrict__ comp,
+                                                       int* first) {
+    for (int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x; v < n;
+         v += int64_t(gridDim.x) * kBlock)
+        atomicMin(first + comp[v], int(v));
+}
+
+constexpr int kUnreached = 0x7fffffff;
+
+__global__ __launch_bounds__(kBlock) void k_bfs_init(int64_t n, const int* __restrict__ comp,
+                                                     const int* __restrict__ first,
+                                                     int* __restrict__ lev) {
+    for (int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x; v < n;
+         v += int64_t(gridDim.x) * kBlock)
+        lev[v] = first[comp[v]] == int(v) ? 0 : kUnreached;
+}
+
+// One breadth-first level: every vertex at level L gives its unreached
+// neighbours level L + 1 (concurrent writers store the same value).  16
+// lanes share a vertex's incidence list; inc_ptr is indexed by vertex here.
+constexpr int kBfsLanes = 16;
+__global__ __launch_bounds__(kBlock) void k_bfs_step(int64_t n, const int* __restrict__ inc_ptr,
+                                                     const Inc* __restrict__ inc, int L, int* lev,
+                                                     int* changed) {
+    constexpr int GPB = kBlock / kBfsLanes;
+    const int gl = threadIdx.x % kBfsLanes;
+    int ch = 0;
+    for (int64_t v = int64_t(blockIdx.x) * GPB + threadIdx.x / kBfsLanes; v < n;
+         v += int64_t(gridDim.x) * GPB) {
+        if (__hip_atomic_load(lev + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != L) continue;
+        const int e1 = inc_ptr[v + 1];
+        for (int p = inc_ptr[v] + gl; p < e1; p += kBfsLanes) {
+            const int o = inc[p].o;
+            if (__hip_atomic_load(lev + o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                kUnreached) {
+                __hip_atomic_store(lev + o, L + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ch = 1;
+            }
+        }
+    }
+    if (ch) atomicOr(changed, 1);
+}
+
+// sort key (component, level) of every vertex; levels past `cap` share cap
+__global__ __launch_bounds__(kBlock) void k_order_keys(int64_t n, const int* __restrict__ comp,
+                                                       const int* __restrict__ lev, int cap,
+                                                       unsigned long long* __restrict__ key,
+                                                       int* __restrict__ val) {
+    for (int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x; v < n;
+         v += int64_t(gridDim.x) * kBlock) {
+        const int l = lev[v] < cap ? lev[v] : cap;
+        key[v] = static_cast<unsigned long long>(comp[v]) * (unsigned long long)(cap + 1) +
+                 static_cast<unsigned long long>(l);
+        val[v] = int(v);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rank_of(int64_t n, const int* __restrict__ vord,
+                                                    int* __restrict__ vrank) {
+    for (int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x; r < n;
+         r += int64_t(gridDim.x) * kBlock)
+        vrank[vord[r]] = int(r);
+}
+
+__global__ __launch_bounds__(kBlock) void k_entry_rank(int64_t cnt, const int* __restrict__ irow,
+                                                       const int* __restrict__ vrank,
+                                                       int* __restrict__ rk) {
+    for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < cnt;
+         p += int64_t(gridDim.x) * kBlock)
+        rk[p] = vrank[irow[p]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_entry_vertex(int64_t cnt, const int* __restrict__ rk,
+                                                         const int* __restrict__ vord,
+                                                         int* __restrict__ irow) {
+    for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < cnt;
+         p += int64_t(gridDim.x) * kBlock)
+        irow[p] = vord[rk[p]];
+}
+
 }  // namespace
 
 namespace {
@@ -402,9 +491,120 @@ ccm_status graph_canonical_count(const int* src, const int* dst, const double* w
     return canonicalize(src, dst, w, m, s, tmp, m_canon, err);
 }
 
+namespace {
+
+// Re-sorts the vertex-ordered incidence lists of `out` (inc_ptr by vertex)
+// into the locality order: connected components by their smallest vertex,
+// inside a component by breadth-first level from that vertex, ties by
+// vertex index.  Neighbours then sit near each other in the order, so the
+// vertex kernels, which run windows of the order roughly in sequence, keep
+// the rows they gather in the caches.  Sets vord, vrank, inc_ptr (by rank),
+// inc, irow and epos.
+ccm_status locality_order(OwnedGraph& out, hipStream_t s, std::string& err) {
+    const int64_t n = out.g.n, m = out.g.m, cnt = out.g.nent;
+    // components of the whole graph (every edge taken as fused)
+    DevMem ones, comp, parent, scan, temp, ncl, first, lev, flag;
+    HIPCHK(ones.alloc(std::max<int64_t>(m, 1) * 4, s));
+    HIPCHK(comp.alloc(n * 4, s));
+    HIPCHK(parent.alloc(n * 4, s));
+    HIPCHK(scan.alloc((n + 1) * 4, s));
+    const size_t tb = labels_temp_bytes(n);
+    HIPCHK(temp.alloc(tb, s));
+    HIPCHK(ncl.alloc(4, s));
+    hipLaunchKernelGGL(k_fill_i32, dim3(flat_grid(m)), dim3(kBlock), 0, s, m, 1, ones.as<int>());
+    launch_labels(n, m, out.g.src, out.g.dst, ones.as<int>(), parent.as<int>(), scan.as<int>(),
+                  temp.p, tb, comp.as<int>(), ncl.as<int>(), s, out.g.inc_ptr, out.g.inc);
+    HIPCHK(hipGetLastError());
+    int K = 0;
+    HIPCHK(hipMemcpyAsync(&K, ncl.p, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (K < 1 || K > n) {
+        err = "internal: component count out of range in the locality order";
+        return CCM_E_HIP;
+    }
+    // breadth-first levels from each component's smallest vertex
+    HIPCHK(first.alloc(size_t(K) * 4, s));
+    HIPCHK(lev.alloc(n * 4, s));
+    HIPCHK(flag.alloc(4, s));
+    hipLaunchKernelGGL(k_fill_i32, dim3(flat_grid(K)), dim3(kBlock), 0, s, int64_t(K), kUnreached,
+                       first.as<int>());
+    hipLaunchKernelGGL(k_comp_first, dim3(flat_grid(n)), dim3(kBlock), 0, s, n, comp.as<int>(),
+                       first.as<int>());
+    hipLaunchKernelGGL(k_bfs_init, dim3(flat_grid(n)), dim3(kBlock), 0, s, n, comp.as<int>(),
+                       first.as<int>(), lev.as<int>());
+    constexpr int kMaxLevels = 4096;  // deeper levels share one key (order only)
+    const int64_t gpb = kBlock / kBfsLanes;
+    const int gb = int(std::min<int64_t>((n + gpb - 1) / gpb, kMaxGrid));
+    int depth = 0;
+    for (int L = 0; L < kMaxLevels; ++L) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, s, int64_t(1), 0, flag.as<int>());
+        hipLaunchKernelGGL(k_bfs_step, dim3(gb), dim3(kBlock), 0, s, n, out.g.inc_ptr, out.g.inc,
+                           L, lev.as<int>(), flag.as<int>());
+        int h = 0;
+        HIPCHK(hipMemcpyAsync(&h, flag.p, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        depth = L + 1;
+        if (!h) break;
+    }
+    // vertices by (component, level), stable in vertex index
+    DevMem key, key_s, val, tmp2;
+    HIPCHK(key.alloc(n * 8, s));
+    HIPCHK(key_s.alloc(n * 8, s));
+    HIPCHK(val.alloc(n * 4, s));
+    HIPCHK(out.vord.alloc(n * 4, s));
+    HIPCHK(out.vrank.alloc(n * 4, s));
+    hipLaunchKernelGGL(k_order_keys, dim3(flat_grid(n)), dim3(kBlock), 0, s, n, comp.as<int>(),
+                       lev.as<int>(), depth, key.as<unsigned long long>(), val.as<int>());
+    const int kb = bits_for(int64_t(K) * (depth + 1));
+    size_t b = 0;
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, b, key.as<unsigned long long>(),
+                                              key_s.as<unsigned long long>(), val.as<int>(),
+                                              out.vord.as<int>(), int(n), 0, kb, s));
+    HIPCHK(tmp2.alloc(b, s));
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(tmp2.p, b, key.as<unsigned long long>(),
+                                              key_s.as<unsigned long long>(), val.as<int>(),
+                                              out.vord.as<int>(), int(n), 0, kb, s));
+    hipLaunchKernelGGL(k_rank_of, dim3(flat_grid(n)), dim3(kBlock), 0, s, n, out.vord.as<int>(),
+                       out.vrank.as<int>());
+    if (cnt > 0) {
+        // entries by the rank of their vertex, stable (each list keeps its
+        // ascending edge order)
+        DevMem rk, rk_s, inc_s, tmp3, maxdeg;
+        HIPCHK(rk.alloc(cnt * 4, s));
+        HIPCHK(rk_s.alloc(cnt * 4, s));
+        HIPCHK(inc_s.alloc(cnt * 8, s));
+        HIPCHK(maxdeg.alloc(4, s));
+        hipLaunchKernelGGL(k_entry_rank, dim3(flat_grid(cnt)), dim3(kBlock), 0, s, cnt,
+                           out.g.irow, out.vrank.as<int>(), rk.as<int>());
+        const int nb = bits_for(n);
+        size_t b3 = 0;
+        HIPCHK(hipcub::DeviceRadixSort::SortPairs(
+            nullptr, b3, rk.as<int>(), rk_s.as<int>(), out.inc.as<unsigned long long>(),
+            inc_s.as<unsigned long long>(), int(cnt), 0, nb, s));
+        HIPCHK(tmp3.alloc(b3, s));
+        HIPCHK(hipcub::DeviceRadixSort::SortPairs(
+            tmp3.p, b3, rk.as<int>(), rk_s.as<int>(), out.inc.as<unsigned long long>(),
+            inc_s.as<unsigned long long>(), int(cnt), 0, nb, s));
+        HIPCHK(hipMemcpyAsync(out.inc.p, inc_s.p, cnt * 8, hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_entry_vertex, dim3(flat_grid(cnt)), dim3(kBlock), 0, s, cnt,
+                           rk_s.as<int>(), out.vord.as<int>(), out.irow.as<int>());
+        hipLaunchKernelGGL(k_epos, dim3(flat_grid(cnt)), dim3(kBlock), 0, s, cnt,
+                           out.inc.as<Inc>(), out.epos.as<int>());
+        HIPCHK(hipMemsetAsync(maxdeg.p, 0, 4, s));
+        hipLaunchKernelGGL(k_inc_ptr, dim3(flat_grid(n + 1)), dim3(kBlock), 0, s, n, cnt,
+                           rk_s.as<int>(), out.inc_ptr.as<int>(), maxdeg.as<int>());
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    out.g.vord = out.vord.as<int>();
+    out.g.vrank = out.vrank.as<int>();
+    return CCM_OK;
+}
+
+}  // namespace
+
 ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t m, int64_t n,
                        int d, bool require_canonical, hipStream_t s, OwnedGraph& out,
-                       std::string& err) {
+                       std::string& err, int locality) {
     if (n < 1 || n > (int64_t(1) << 30) || m < 0 || m > (int64_t(1) << 30)) {
         err = "graph size out of range";
         return CCM_E_INVALID;
@@ -468,6 +668,10 @@ ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t 
     out.g.epos = out.epos.as<int>();
     out.g.max_deg = md;
     out.g.nent = cnt;
+    if (locality > 0 || (locality < 0 && n * int64_t(d) >= kLocalityMin)) {
+        st = locality_order(out, s, err);
+        if (st != CCM_OK) return st;
+    }
     return build_windows(d, s, out, err);
 }
 
@@ -483,17 +687,21 @@ ccm_status build_windows(int d, hipStream_t s, OwnedGraph& out, std::string& err
         return CCM_E_HIP;
     }
     const int64_t S = window_for(d);
-    std::vector<int> ptr(size_t(n) + 1);
+    std::vector<int> ptr(size_t(n) + 1), vord;
     HIPCHK(hipMemcpyAsync(ptr.data(), out.g.inc_ptr, ptr.size() * 4, hipMemcpyDeviceToHost, s));
+    if (out.g.vord) {
+        vord.resize(size_t(n));
+        HIPCHK(hipMemcpyAsync(vord.data(), out.g.vord, size_t(n) * 4, hipMemcpyDeviceToHost, s));
+    }
     HIPCHK(hipStreamSynchronize(s));
     std::vector<int2> win;
     std::vector<int> iso;
     win.reserve(size_t(cnt / S + 2));
     int64_t ws = 0;
-    for (int64_t v = 0; v < n; ++v) {
-        const int64_t b = ptr[v], e = ptr[v + 1];
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t b = ptr[r], e = ptr[r + 1];
         if (e == b) {
-            iso.push_back(int(v));
+            iso.push_back(vord.empty() ? int(r) : vord[size_t(r)]);
             continue;
         }
         if (e - ws > S && b > ws) {
@@ -502,9 +710,18 @@ ccm_status build_windows(int d, hipStream_t s, OwnedGraph& out, std::string& err
         }
     }
     if (cnt > ws) win.push_back(int2{int(ws), int(cnt)});
-    // longest first, ties in entry order
-    std::stable_sort(win.begin(), win.end(),
-                     [](const int2& a, const int2& b) { return a.y - a.x > b.y - b.x; });
+    if (out.g.vord) {
+        // hub windows first (their long serial work starts early), then the
+        // locality order: workgroups are dispatched in window order, so the
+        // windows in flight at any time are neighbours in that order
+        std::stable_partition(win.begin(), win.end(),
+                              [S](const int2& a) { return int64_t(a.y) - a.x > S; });
+    } else {
+        // input order: longest first (short windows fill the tail), ties in
+        // entry order
+        std::stable_sort(win.begin(), win.end(),
+                         [](const int2& a, const int2& b) { return a.y - a.x > b.y - b.x; });
+    }
     HIPCHK(out.win.alloc(std::max<size_t>(win.size(), 1) * 8, s));
     HIPCHK(out.iso.alloc(std::max<size_t>(iso.size(), 1) * 4, s));
     if (!win.empty())

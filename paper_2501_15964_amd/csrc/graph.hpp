@@ -42,17 +42,24 @@ struct DevMem {
 
 struct OwnedGraph {
     DevGraph g;
-    DevMem src, dst, w, inc_ptr, inc, irow, epos, win, iso;
+    DevMem src, dst, w, inc_ptr, inc, irow, epos, win, iso, vord, vrank;
 };
 
 // Builds `out` from caller edges for rows of d values.  With
 // require_canonical the edges must already be canonical (src < dst, strictly
 // increasing (src, dst), w > 0) and are referenced in place; otherwise they
-// are canonicalised into owned arrays.  Returns CCM_OK or an error with text
+// are canonicalised into owned arrays.  `locality` selects the processing
+// order of the vertices in the incidence lists: 0 the input order, 1 a
+// locality order (connected components one after another, each in
+// breadth-first levels from its smallest vertex, ties by vertex index), -1
+// the locality order when n d >= kLocalityMin.  The order changes which
+// vertices the vertex kernels work on at the same time (and so what the
+// caches hold), never the data layout.  Returns CCM_OK or an error with text
 // in `err`.  Synchronises s.
+constexpr int64_t kLocalityMin = int64_t(1) << 22;
 ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t m, int64_t n,
                        int d, bool require_canonical, hipStream_t s, OwnedGraph& out,
-                       std::string& err);
+                       std::string& err, int locality = -1);
 
 // Window split (win, iso) of out.g's incidence lists for rows of d values;
 // needs out.g.n, nent, inc_ptr, inc, irow.  Synchronises s.

@@ -53,21 +53,24 @@ __global__ __launch_bounds__(kBlock) void k_uf_init(int64_t n, int* parent) {
 }
 
 // First hooking, without atomics: every vertex points at its smallest fused
-// neighbour (or at itself); 16 lanes share a vertex's incidence list.
-// Pointers decrease, so this is a forest inside the components, and most
-// fused edges then join vertices of one tree.
+// neighbour (or at itself); 16 lanes share a vertex's incidence list (the
+// lists are indexed by rank r, of vertex vord[r], or by vertex if vord is
+// null).  Pointers decrease, so this is a forest inside the components, and
+// most fused edges then join vertices of one tree.
 constexpr int kHookLanes = 16;
 __global__ __launch_bounds__(kBlock) void k_uf_hook_min(int64_t n, const int* __restrict__ inc_ptr,
                                                         const Inc* __restrict__ inc,
+                                                        const int* __restrict__ vord,
                                                         const int* __restrict__ fused,
                                                         int* __restrict__ parent) {
     const int gl = threadIdx.x % kHookLanes;
     constexpr int GPB = kBlock / kHookLanes;
-    for (int64_t v = int64_t(blockIdx.x) * GPB + threadIdx.x / kHookLanes; v < n;
-         v += int64_t(gridDim.x) * GPB) {
+    for (int64_t r = int64_t(blockIdx.x) * GPB + threadIdx.x / kHookLanes; r < n;
+         r += int64_t(gridDim.x) * GPB) {
+        const int64_t v = vord ? vord[r] : r;
         int mn = int(v);
-        const int e1 = inc_ptr[v + 1];
-        for (int p = inc_ptr[v] + gl; p < e1; p += kHookLanes) {
+        const int e1 = inc_ptr[r + 1];
+        for (int p = inc_ptr[r] + gl; p < e1; p += kHookLanes) {
             const Inc e = inc[p];
             const int l = e.e >= 0 ? e.e : ~e.e;
             if (fused[l] && e.o < mn) mn = e.o;
@@ -164,7 +167,8 @@ size_t labels_temp_bytes(int64_t n) {
 
 void launch_labels(int64_t n, int64_t m, const int* src, const int* dst, const int* fused,
                    int* parent, int* rank, void* temp, size_t temp_bytes, int* labels,
-                   int* n_clusters, hipStream_t s, const int* inc_ptr, const Inc* inc) {
+                   int* n_clusters, hipStream_t s, const int* inc_ptr, const Inc* inc,
+                   const int* vord) {
     // rank holds n + 1 ints: [0, n) the scan output, [n] the last root flag.
     // The root flags themselves live in `labels` until the final pass
     // overwrites them with the labels.
@@ -173,8 +177,8 @@ void launch_labels(int64_t n, int64_t m, const int* src, const int* dst, const i
     if (inc_ptr && inc && m > 0) {
         const int64_t gpb = kBlock / kHookLanes;
         const int gh = int(std::min<int64_t>((n + gpb - 1) / gpb, kMaxGrid));
-        hipLaunchKernelGGL(k_uf_hook_min, dim3(gh), dim3(kBlock), 0, s, n, inc_ptr, inc, fused,
-                           parent);
+        hipLaunchKernelGGL(k_uf_hook_min, dim3(gh), dim3(kBlock), 0, s, n, inc_ptr, inc, vord,
+                           fused, parent);
         hipLaunchKernelGGL(k_uf_jump, dim3(g), dim3(kBlock), 0, s, n, parent);
         for (int round = 0; round < 2; ++round) {
             hipLaunchKernelGGL(k_uf_hook_edges, dim3(flat_grid(m)), dim3(kBlock), 0, s, m, src,

@@ -15,7 +15,9 @@ using IC = std::integral_constant<int, V>;
 // Row layout: LPR lanes of a wave handle one row of d values, NPER values
 // per lane (coordinate k = lane_in_group + LPR * t).  Up to 256 values a lane
 // holds at most 4, so a wave works on several rows at once and the per-row
-// reductions stay short; longer rows use the whole wave.
+// reductions stay short; longer rows use the whole wave, with no more values
+// per lane than the row needs in steps that keep registers (and so waves in
+// flight) for the common widths.
 inline bool row_supported(int64_t d) { return d >= 1 && d <= 1024; }
 
 template <class F>
@@ -29,6 +31,8 @@ inline void dispatch_row(int d, F&& f) {
     else if (d <= 128) f(IC<32>{}, IC<4>{});
     else if (d <= 256) f(IC<64>{}, IC<4>{});
     else if (d <= 512) f(IC<64>{}, IC<8>{});
+    else if (d <= 768) f(IC<64>{}, IC<12>{});
+    else if (d <= 832) f(IC<64>{}, IC<13>{});
     else f(IC<64>{}, IC<16>{});
 }
 
@@ -85,9 +89,15 @@ struct DevGraph {
     const int* src = nullptr;
     const int* dst = nullptr;
     const double* w = nullptr;
-    const int* inc_ptr = nullptr;  // n + 1
+    // The incidence lists are stored in a processing order of the vertices:
+    // vertex vord[r] has rank r and its entries are inc[inc_ptr[r] ..
+    // inc_ptr[r + 1]); vrank is the inverse map.  Null vord / vrank mean the
+    // identity order (rank = vertex).
+    const int* inc_ptr = nullptr;  // n + 1, by rank
     const Inc* inc = nullptr;      // 2 m
     const int* irow = nullptr;     // vertex of each incidence entry (2 m)
+    const int* vord = nullptr;     // n: vertex of each rank (null: identity)
+    const int* vrank = nullptr;    // n: rank of each vertex (null: identity)
     const int* epos = nullptr;     // incidence positions of edge l: [2 l] at src, [2 l + 1] at dst
     int max_deg = 0;
     // Work split of the incidence array for the vertex kernels: window w holds
@@ -95,15 +105,25 @@ struct DevGraph {
     // window_for(d) of them unless the window is a single hub vertex.  One
     // workgroup takes a window; its row groups split the window's entries
     // evenly, and a vertex cut between row groups is summed through LDS, in
-    // row-group order, by the group where it starts.  Windows are stored
-    // longest first (hubs start early).  Isolated vertices have no entries
-    // and are listed in `iso`.
+    // row-group order, by the group where it starts.  With a locality order
+    // (vord set) windows follow it, except that hub windows (longer than
+    // window_for(d)) come first; in the input order they are stored longest
+    // first.  Isolated vertices have no entries and are listed in `iso`.
     int64_t nent = 0;            // incidence entries (2 m for an edge graph)
     const int2* win = nullptr;   // nwin non-empty windows
     int64_t nwin = 0;
     const int* iso = nullptr;    // vertices without incidences
     int64_t niso = 0;
 };
+
+// Doubles of a partials buffer that a kernel over graph g may fill: the
+// vertex kernels run one workgroup per window (or per row group of isolated
+// vertices), up to 8 values each; the other kernels stay within kPartialsCap.
+inline size_t partials_for(const DevGraph& g) {
+    const int64_t b = (g.nwin > g.niso ? g.nwin : g.niso) + 1;
+    const size_t need = size_t(b) * 8 * 2;
+    return need > size_t(kPartialsCap) ? need : size_t(kPartialsCap);
+}
 
 // incidences per row group of a window: about one typical vertex for long
 // rows, several short vertices for short rows
@@ -177,7 +197,7 @@ struct CgSkip {
 };
 constexpr int kMatvecNV = 1;
 // SSNAL edge pass fused with the gradient (one launch, vertex-centric; q = 1
-// or 2, any other qk is taken as 2): Pi =
+// or 2 only: for q = inf nothing is launched and -1 is returned): Pi =
 // Pi_C(U + sigma B X) and its Jacobian payload as launch_edge_ssnal, G = X -
 // A + B^T Pi and Dinv as launch_scatter(diag); edge partials (kEdgeSsnalNV)
 // to epart and vertex partials (kScatterNV) to spart, one row per block;
@@ -293,6 +313,7 @@ size_t labels_temp_bytes(int64_t n);
 void launch_labels(int64_t n, int64_t m, const int* src, const int* dst, const int* fused,
                    int* parent, int* rank, void* temp, size_t temp_bytes, int* labels,
                    int* n_clusters, hipStream_t s,
-                   const int* inc_ptr = nullptr, const Inc* inc = nullptr);
+                   const int* inc_ptr = nullptr, const Inc* inc = nullptr,
+                   const int* vord = nullptr);
 
 }  // namespace ccm

@@ -263,7 +263,7 @@ struct Solver::Impl {
         HIPCHK(rank.alloc((n + 1) * 4, s));
         ltemp_bytes = labels_temp_bytes(n);
         HIPCHK(ltemp.alloc(ltemp_bytes, s));
-        const size_t pb = size_t(kPartialsCap) * 8;
+        const size_t pb = partials_for(g) * 8;
         for (DevMem* b : {&pe, &pet, &ps, &pst, &pt, &pk, &pm, &pm2, &pupd0, &pupd1, &pwu0, &pwu1})
             HIPCHK(b->alloc(pb, s));
         HIPCHK(cgstate.alloc(8 * 8, s));
@@ -1042,7 +1042,7 @@ struct Solver::Impl {
             lab = scratch.as<int>();
         }
         launch_labels(n, m, g.src, g.dst, fused.as<int>(), parent.as<int>(), rank.as<int>(),
-                      ltemp.p, ltemp_bytes, lab, cgflag.as<int>() + 2, s, g.inc_ptr, g.inc);
+                      ltemp.p, ltemp_bytes, lab, cgflag.as<int>() + 2, s, g.inc_ptr, g.inc, g.vord);
         HIPCHK(hipMemcpyAsync(hflag + 2, cgflag.as<int>() + 2, sizeof(int), hipMemcpyDeviceToHost,
                               s));
         HIPCHK(hipStreamSynchronize(s));

@@ -224,13 +224,15 @@ __global__ __launch_bounds__(kBlock) void k_sub(const double* __restrict__ a,
 }
 
 __global__ __launch_bounds__(kBlock) void k_lap_dinv(int64_t n, int d,
-                                                     const int* __restrict__ inc_ptr, double c0,
+                                                     const int* __restrict__ inc_ptr,
+                                                     const int* __restrict__ vrank, double c0,
                                                      double sigma, double* __restrict__ Dinv) {
     const int64_t N = n * d;
     for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
          k += int64_t(gridDim.x) * kBlock) {
         const int64_t i = k / d;
-        Dinv[k] = 1.0 / (c0 + sigma * double(inc_ptr[i + 1] - inc_ptr[i]));
+        const int64_t r = vrank ? vrank[i] : i;
+        Dinv[k] = 1.0 / (c0 + sigma * double(inc_ptr[r + 1] - inc_ptr[r]));
     }
 }
 
@@ -483,7 +485,7 @@ void launch_sub(const double* a, const double* b, double* out, int64_t N, hipStr
 void launch_lap_dinv(const DevGraph& g, int d, double c0, double sigma, double* Dinv,
                      hipStream_t s) {
     hipLaunchKernelGGL(k_lap_dinv, dim3(flat_grid(g.n * d)), dim3(kBlock), 0, s, g.n, d,
-                       g.inc_ptr, c0, sigma, Dinv);
+                       g.inc_ptr, g.vrank, c0, sigma, Dinv);
 }
 
 int spread_work_size(int64_t n, int d) { return kSpreadBlocks * d + d + kSpreadBlocks; }

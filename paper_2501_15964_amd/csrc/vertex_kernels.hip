@@ -140,6 +140,13 @@ __device__ __forceinline__ Meta chunk_meta_get(const ChunkMeta<LPR, NM>& cm, int
     e = __shfl(e, src, LPR);
     m.o = __shfl(o, src, LPR);
     m.v = __shfl(v, src, LPR);
+    if constexpr (LPR == 64) {
+        // a whole wave shares the entry: keep its indices in scalar registers,
+        // so row addresses are a scalar base plus the lane's offset
+        e = __builtin_amdgcn_readfirstlane(e);
+        m.o = __builtin_amdgcn_readfirstlane(m.o);
+        m.v = __builtin_amdgcn_readfirstlane(m.v);
+    }
     m.pos = e >= 0;
     m.l = m.pos ? e : ~e;
     m.a = 1.0;
@@ -406,14 +413,20 @@ struct EdgeGradUnroll {
 // With KKT, the first endpoint also adds the edge's terms of the KKT
 // residuals at (X, U) (as k_edge_kkt: ||Pi_C(BX + U) - U||^2, ||BX||^2,
 // ||U||^2, ||U - Pi_C(U)||^2, r ||(BX)_l||_q) into kpart.
+// (rows of up to 13 values per lane are held to two waves per SIMD)
+template <int NPER>
+constexpr int edge_grad_min_waves() { return NPER <= 13 ? 2 : 1; }
+
 template <int LPR, int NPER, int Q, bool KKT>
-__global__ __launch_bounds__(kBlock) void k_edge_grad_win(DevGraph g, int d, ScatterOut so,
+__global__ __launch_bounds__(kBlock, edge_grad_min_waves<NPER>()) void k_edge_grad_win(
+                                                          DevGraph g, int d, ScatterOut so,
                                                           double gamma,
                                                           const double* __restrict__ U,
                                                           double* __restrict__ Pi, Payload pl,
                                                           double* __restrict__ epart,
                                                           double* __restrict__ spart,
                                                           double* __restrict__ kpart) {
+    static_assert(Q == kQ1 || Q == kQ2, "the fused edge pass serves q = 1 and q = 2");
     constexpr int UB = EdgeGradUnroll<NPER>::U;
     constexpr int NM = meta_slots<LPR, NPER>();
     constexpr bool PF = NM <= 4;
@@ -426,7 +439,17 @@ __global__ __launch_bounds__(kBlock) void k_edge_grad_win(DevGraph g, int d, Sca
     const double sigma = so.sigma;
     double acc4[kScatterNV] = {0.0, 0.0, 0.0, 0.0};
     double eacc[kEdgeSsnalNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    double kacc[kEdgeKktNV] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // the KKT sums of each lane live in LDS (one slot per lane and term,
+    // touched only by its lane, in program order), not in registers
+    __shared__ double kl[KKT ? 4 : 1][kBlock];
+    if constexpr (KKT) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) kl[c][threadIdx.x] = 0.0;
+    }
+    auto kadd = [&](int c, double v) {
+        __hip_atomic_fetch_add(&kl[c][threadIdx.x], v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
     for (int w = blockIdx.x; w < int(g.nwin); w += gridDim.x) {
         const GroupRange gr = group_range(g, w, rg, GPB);
         int vcur = -1;
@@ -435,7 +458,16 @@ __global__ __launch_bounds__(kBlock) void k_edge_grad_win(DevGraph g, int d, Sca
         double acc[NPER], dg[NPER], xr[NPER], ar[NPER];
 #pragma unroll
         for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = xr[t] = ar[t] = 0.0;
-        auto finish = [&]() { scatter_finish<LPR, NPER, true>(vcur, d, gl, so, xr, ar, acc, dg, acc4); };
+        // long rows read A only when the vertex is finished (registers)
+        auto finish = [&]() {
+            if constexpr (Unroll<NPER>::PREFETCH) {
+                scatter_finish<LPR, NPER, true>(vcur, d, gl, so, xr, ar, acc, dg, acc4);
+            } else {
+                double a2[NPER];
+                load_row<LPR, NPER>(so.A, vcur, d, gl, a2);
+                scatter_finish<LPR, NPER, true>(vcur, d, gl, so, xr, a2, acc, dg, acc4);
+            }
+        };
         auto done = [&](bool cut_start) {
             if (!cut_start) {
                 finish();
@@ -486,50 +518,60 @@ __global__ __launch_bounds__(kBlock) void k_edge_grad_win(DevGraph g, int d, Sca
                         }
                         vcur = m.v;
                         load_row<LPR, NPER>(so.X, vcur, d, gl, xr);
-                        load_row<LPR, NPER>(so.A, vcur, d, gl, ar);
+                        if constexpr (Unroll<NPER>::PREFETCH)
+                            load_row<LPR, NPER>(so.A, vcur, d, gl, ar);
 #pragma unroll
                         for (int t = 0; t < NPER; ++t) acc[t] = dg[t] = 0.0;
                     }
                     // the edge's row, oriented first endpoint minus second
                     const double r = gamma * wl[u];
-                    double bx[NPER], y[NPER];
+                    double bx[NPER], pi[NPER];
 #pragma unroll
                     for (int t = 0; t < NPER; ++t) {
                         bx[t] = m.pos ? xr[t] - xo[u][t] : xo[u][t] - xr[t];
-                        y[t] = ur[u][t] + sigma * bx[t];
+                        pi[t] = ur[u][t] + sigma * bx[t];
                     }
-                    RowProj<LPR, NPER, Q> o;
-                    project_row<LPR, NPER, Q, true>(y, gl, lane, d, r, o);
+                    // projection onto the dual ball in place (the same
+                    // arithmetic as project_row): q = 2 scales by
+                    // min(1, r / ||y||), q = 1 clamps to [-r, r]
+                    double alpha = 1.0;
+                    uint32_t lm = 0u;
+                    if constexpr (Q == kQ2) {
+                        double s2 = 0.0;
 #pragma unroll
-                    for (int t = 0; t < NPER; ++t) acc[t] += m.pos ? o.pi[t] : -o.pi[t];
+                        for (int t = 0; t < NPER; ++t) s2 += pi[t] * pi[t];
+                        const double nrm = sqrt(group_sum<LPR>(s2));
+                        if (nrm > r) {
+                            alpha = r / nrm;
+#pragma unroll
+                            for (int t = 0; t < NPER; ++t) pi[t] *= alpha;
+                        }
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < NPER; ++t) {
+                            if (gl + LPR * t < d && fabs(pi[t]) <= r) lm |= 1u << t;
+                            pi[t] = fmin(fmax(pi[t], -r), r);
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < NPER; ++t) acc[t] += m.pos ? pi[t] : -pi[t];
                     if constexpr (Q == kQ2) {
                         const double ir = 1.0 / r;
-                        if (o.alpha >= 1.0) {
+                        if (alpha >= 1.0) {
 #pragma unroll
                             for (int t = 0; t < NPER; ++t) dg[t] += 1.0;
-                        } else if (o.alpha > 0.0) {
+                        } else if (alpha > 0.0) {
 #pragma unroll
                             for (int t = 0; t < NPER; ++t) {
-                                const double yh = o.pi[t] * ir;
-                                dg[t] += o.alpha * (1.0 - yh * yh);
+                                const double yh = pi[t] * ir;
+                                dg[t] += alpha * (1.0 - yh * yh);
                             }
                         }
-                        if (gl == 0) pl.ipay[p0 + u] = double2{o.alpha, ir};
-                    } else if constexpr (Q == kQ1) {
+                        if (gl == 0) pl.ipay[p0 + u] = double2{alpha, ir};
+                    } else {
 #pragma unroll
                         for (int t = 0; t < NPER; ++t)
-                            if ((o.lm >> t) & 1u) dg[t] += 1.0;
-                    } else {
-                        if (o.cnt < 0) {
-#pragma unroll
-                            for (int t = 0; t < NPER; ++t) dg[t] += 1.0;
-                        } else if (o.cnt > 0) {
-                            const double f = 1.0 - 1.0 / double(o.cnt);
-#pragma unroll
-                            for (int t = 0; t < NPER; ++t)
-                                if ((o.lm >> t) & 1u) dg[t] += f;
-                        }
-                        if (gl == 0) pl.ipay[p0 + u] = double2{double(o.cnt), 0.0};
+                            if ((lm >> t) & 1u) dg[t] += 1.0;
                     }
                     if (m.pos) {
                         const int64_t l = m.l;
@@ -537,45 +579,65 @@ __global__ __launch_bounds__(kBlock) void k_edge_grad_win(DevGraph g, int d, Sca
                         for (int t = 0; t < NPER; ++t) {
                             const int k = gl + LPR * t;
                             if (k < d) {
-                                Pi[l * d + k] = o.pi[t];
-                                const double e = o.pi[t] - ur[u][t];
-                                eacc[0] += bx[t] * o.pi[t];
+                                Pi[l * d + k] = pi[t];
+                                const double e = pi[t] - ur[u][t];
+                                eacc[0] += bx[t] * pi[t];
                                 eacc[1] += e * e;
                                 eacc[2] += bx[t] * bx[t];
-                                eacc[3] += o.pi[t] * o.pi[t];
+                                eacc[3] += pi[t] * pi[t];
                             }
                         }
-                        if constexpr (Q != kQ2) pl.lbits[l * LPR + gl] = o.lm;
+                        if constexpr (Q != kQ2) pl.lbits[l * LPR + gl] = lm;
                         if (gl == 0) {
-                            if constexpr (Q == kQ2) eacc[4] += (o.alpha < 1.0) ? 1.0 : 0.0;
-                            else if constexpr (Q == kQInf) eacc[4] += (o.cnt >= 0) ? 1.0 : 0.0;
+                            if constexpr (Q == kQ2) eacc[4] += (alpha < 1.0) ? 1.0 : 0.0;
                             else eacc[4] += 1.0;
                         }
                         if constexpr (KKT) {
-                            double v[NPER], nq = 0.0;
+                            // the edge's KKT terms at (X, U): v = (BX)_l + u_l and
+                            // the projections of v and u_l, coordinate by
+                            // coordinate (q = 2 scales by the row norms, q = 1
+                            // clamps), so no projected row is held in registers
+                            double nq = 0.0, sv = 0.0, su = 0.0;
 #pragma unroll
                             for (int t = 0; t < NPER; ++t) {
-                                v[t] = bx[t] + ur[u][t];
-                                if constexpr (Q == kQ1) nq += fabs(bx[t]);
-                                else nq += bx[t] * bx[t];
+                                const double vt = bx[t] + ur[u][t];
+                                if constexpr (Q == kQ1) {
+                                    nq += fabs(bx[t]);
+                                } else {
+                                    nq += bx[t] * bx[t];
+                                    sv += vt * vt;
+                                    su += ur[u][t] * ur[u][t];
+                                }
                             }
-                            double pen;
-                            if constexpr (Q == kQ2) pen = r * sqrt(group_sum<LPR>(nq));
-                            else pen = group_sum<LPR>(r * nq);
-                            if (gl == 0) kacc[4] += pen;
-                            RowProj<LPR, NPER, Q> pv, pu;
-                            project_row<LPR, NPER, Q, false>(v, gl, lane, d, r, pv);
-                            project_row<LPR, NPER, Q, false>(ur[u], gl, lane, d, r, pu);
+                            double pen, av = 1.0, au = 1.0;
+                            if constexpr (Q == kQ2) {
+                                pen = r * sqrt(group_sum<LPR>(nq));
+                                const double nv = sqrt(group_sum<LPR>(sv));
+                                const double nu = sqrt(group_sum<LPR>(su));
+                                if (nv > r) av = r / nv;
+                                if (nu > r) au = r / nu;
+                            } else {
+                                pen = group_sum<LPR>(r * nq);
+                            }
+                            if (gl == 0) kadd(3, pen);
 #pragma unroll
                             for (int t = 0; t < NPER; ++t) {
                                 const int k = gl + LPR * t;
                                 if (k < d) {
-                                    const double e = pv.pi[t] - ur[u][t];
-                                    const double f = ur[u][t] - pu.pi[t];
-                                    kacc[0] += e * e;
-                                    kacc[1] += bx[t] * bx[t];
-                                    kacc[2] += ur[u][t] * ur[u][t];
-                                    kacc[3] += f * f;
+                                    const double vt = bx[t] + ur[u][t];
+                                    double pvt, put;
+                                    if constexpr (Q == kQ2) {
+                                        pvt = av < 1.0 ? vt * av : vt;
+                                        put = au < 1.0 ? ur[u][t] * au : ur[u][t];
+                                    } else {
+                                        pvt = fmin(fmax(vt, -r), r);
+                                        put = fmin(fmax(ur[u][t], -r), r);
+                                    }
+                                    const double e = pvt - ur[u][t];
+                                    const double f = ur[u][t] - put;
+                                    kadd(0, e * e);
+                                    kadd(1, ur[u][t] * ur[u][t]);
+                                    kadd(2, f * f);
                                 }
                             }
                         }
@@ -615,7 +677,12 @@ __global__ __launch_bounds__(kBlock) void k_edge_grad_win(DevGraph g, int d, Sca
     }
     block_reduce_store<kScatterNV>(acc4, spart + blockIdx.x * kScatterNV);
     block_reduce_store<kEdgeSsnalNV>(eacc, epart + blockIdx.x * kEdgeSsnalNV);
-    if constexpr (KKT) block_reduce_store<kEdgeKktNV>(kacc, kpart + blockIdx.x * kEdgeKktNV);
+    if constexpr (KKT) {
+        // ||BX||^2 over the first endpoints' rows is the edge pass's own sum
+        double kacc[kEdgeKktNV] = {kl[0][threadIdx.x], eacc[2], kl[1][threadIdx.x],
+                                   kl[2][threadIdx.x], kl[3][threadIdx.x], 0.0};
+        block_reduce_store<kEdgeKktNV>(kacc, kpart + blockIdx.x * kEdgeKktNV);
+    }
 }
 
 // ---- Newton matvec ------------------------------------------------------------
@@ -707,8 +774,12 @@ __device__ __forceinline__ void matvec_term(const Meta& m, const double (&dl)[NP
     }
 }
 
+// rows of 9 to 13 values per lane: held to three waves per SIMD
+template <int NPER>
+constexpr int matvec_min_waves() { return NPER > 8 && NPER <= 13 ? 3 : 1; }
+
 template <int LPR, int NPER, int Q, int MODE>
-__global__ __launch_bounds__(kBlock) void k_matvec_win(DevGraph g, int d,
+__global__ __launch_bounds__(kBlock, matvec_min_waves<NPER>()) void k_matvec_win(DevGraph g, int d,
                                                        const double* __restrict__ V,
                                                        const double* __restrict__ Pi,
                                                        Payload pl, MatvecOut mo,
@@ -856,12 +927,14 @@ __global__ __launch_bounds__(kBlock) void k_matvec_win(DevGraph g, int d,
 
 }  // namespace
 
-// one workgroup per window, enough to give every isolated vertex a row group
+// one workgroup per window, enough to give every isolated vertex a row
+// group.  Workgroups are dispatched in window order, so the windows in flight
+// at any time are neighbours in the graph's processing order.
 template <int LPR>
 static int window_grid(const DevGraph& g) {
     const int64_t gpb = kBlock / LPR;
-    int64_t b = std::max<int64_t>(g.nwin, (g.niso + gpb - 1) / gpb);
-    return int(std::min<int64_t>(std::max<int64_t>(b, 1), kMaxGrid));
+    const int64_t b = std::max<int64_t>(g.nwin, (g.niso + gpb - 1) / gpb);
+    return int(std::max<int64_t>(b, 1));
 }
 
 int launch_scatter(const DevGraph& g, int d, int qk, double cx, const double* X, double ca,
@@ -907,9 +980,12 @@ int launch_edge_grad(const DevGraph& g, int d, int qk, double gamma, double sigm
         if (qk == kQ1) {
             if (kpart) go(IC<kQ1>{}, IC<1>{});
             else go(IC<kQ1>{}, IC<0>{});
-        } else {
+        } else if (qk == kQ2) {
             if (kpart) go(IC<kQ2>{}, IC<1>{});
             else go(IC<kQ2>{}, IC<0>{});
+        } else {
+            total = -1;  // q = inf has no fused pass (the caller runs two kernels)
+            return;
         }
         total = g1;
     });

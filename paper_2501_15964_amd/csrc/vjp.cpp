@@ -10,6 +10,7 @@
 // with the membership lists.  Then dL/da_i = lambda_{c(i)},
 // dL/dlog w_l = -gamma w_l <lambda_ci - lambda_cj, ghat_l>, and
 // dL/dgamma = -sum_l w_l <lambda_ci - lambda_cj, ghat_l>.
+#include <algorithm>
 #include "vjp.hpp"
 
 #include <cmath>
@@ -71,7 +72,7 @@ ccm_status path_vjp(const double* A, int64_t n, int d, const int* src, const int
         HIPCHK(pv.alloc(size_t(NV) * 8, s));
         HIPCHK(ov.alloc(size_t(NV) * 8, s));
         HIPCHK(minv.alloc(size_t(K) * 8, s));
-        HIPCHK(part.alloc(size_t(kPartialsCap) * 8, s));
+        HIPCHK(part.alloc(std::max(partials_for(og.g), partials_for(cg.g)) * 8, s));
         HIPCHK(sc.alloc(8 * 8, s));
         double* hs = nullptr;
         HIPCHK(hipHostMalloc((void**)&hs, 8 * 8, hipHostMallocDefault));
