@@ -56,7 +56,9 @@ enum {
     CCM_E_UNSUPPORTED = 2,  /* valid request outside what the library implements */
     CCM_E_HIP = 3,          /* a HIP runtime call failed */
     CCM_E_NOMEM = 4,        /* device allocation failed */
-    CCM_E_CAPACITY = 5      /* a caller buffer is too small (see *_cap arguments) */
+    CCM_E_CAPACITY = 5,     /* a caller buffer is too small (see *_cap arguments) */
+    CCM_E_NOT_CONVERGED = 6 /* an iterative solve inside the call stopped before its
+                               tolerance (outputs hold its last iterate) */
 };
 
 enum { CCM_SSNAL = 0, CCM_ADMM = 1, CCM_AMA = 2 };            /* solver */
@@ -270,13 +272,20 @@ ccm_status ccm_solve_path_batched(const ccm_instance* inst_host, int32_t n_inst,
  * tol, max_iter      : CG stop at ||residual|| <= tol ||g|| or max_iter iterations.
  * iters_host         : CG iterations used (may be NULL).
  * Errors: CCM_E_UNSUPPORTED for q != 2; CCM_E_INVALID (sizes, non-canonical
- * edges, labels out of range).  Synchronises `stream`.
+ * edges, labels out of range); CCM_E_NOT_CONVERGED when the CG reached
+ * max_iter or broke down (p.Hp <= 0) before ||residual|| <= tol ||g||: the
+ * gradients are then written from its last iterate.  Synchronises `stream`.
  */
 ccm_status ccm_path_vjp(const double* A, int64_t n, int64_t d, const int32_t* src,
                         const int32_t* dst, const double* w, int64_t m, double gamma, double q,
                         const double* X, const int32_t* labels, const double* dL_dX,
                         double* dL_dA, double* dL_dlogw, double* dL_dgamma_host, double tol,
                         int32_t max_iter, int32_t* iters_host, hipStream_t stream);
+
+/* w_l = exp(log_w_l) for l < m (device arrays): the edge weights of a model
+ * parameterised by log weights (as the autograd wrapper of the binding is),
+ * computed in the library.  Errors: CCM_E_INVALID (m < 0). */
+ccm_status ccm_weights_from_log(const double* log_w, int64_t m, double* w, hipStream_t stream);
 
 /* Number of canonical edges the library derives from (src, dst, w); the
  * row count of each U_out block.  Synchronises `stream`. */

@@ -23,7 +23,10 @@ __all__ = [
     "ccm_op_scatter", "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy",
     "ccm_path_vjp", "CCMSolve", "ccm_solve_path_batched", "CcmInstance", "EXPORTED_SYMBOLS",
     "ccm_build_knn_graph_u8", "ccm_release_workspace",
+    "ccm_weights_from_log", "CCM_E_NOT_CONVERGED",
 ]
+
+CCM_E_NOT_CONVERGED = 6
 
 CCM_SSNAL, CCM_ADMM, CCM_AMA = 0, 1, 2
 CCM_CONVERGED, CCM_MAX_ITER, CCM_TIMEOUT, CCM_NUMERICAL = 0, 1, 2, 3
@@ -38,6 +41,7 @@ EXPORTED_SYMBOLS = [
     "ccm_op_gather", "ccm_op_project", "ccm_op_prox", "ccm_op_scatter",
     "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy", "ccm_path_vjp",
     "ccm_solve_path_batched", "ccm_build_knn_graph_u8", "ccm_release_workspace",
+    "ccm_weights_from_log",
 ]
 
 
@@ -118,6 +122,7 @@ def lib():
         "ccm_op_hess_matvec": [P, P, I64, I64, P, P, P, I64, F64, F64, F64, P, P, I32, P, P],
         "ccm_kkt": [P, P, P, I64, I64, P, P, P, I64, F64, F64, P, P],
         "ccm_labels": [P, P, I64, I64, P, P, I64, P, P, P],
+        "ccm_weights_from_log": [P, I64, P, P],
         "ccm_stream_copy": [P, P, I64, I32, P, P],
         "ccm_path_vjp": [P, I64, I64, P, P, P, I64, F64, F64, P, P, P, P, P, P, F64, I32, P, P],
         "ccm_solve_path_batched": [P, I32, P, P, P, P, P, I32, F64, P, P, P, P, P, P, P],
@@ -173,6 +178,32 @@ def _i32(t):
     if t.dtype != torch.int32:
         raise ValueError("int32 tensor expected")
     return t
+
+
+def _graph_args(A, src, dst, w):
+    """dtype and shape checks of a point set and its edge list (before any
+    device call): A float64 [n, d]; src, dst int32 [m]; w float64 [m]."""
+    _f64(A)
+    if A.dim() != 2:
+        raise ValueError("A must be a 2-D [n, d] tensor")
+    _i32(src)
+    _i32(dst)
+    _f64(w)
+    if src.dim() != 1 or dst.dim() != 1 or w.dim() != 1:
+        raise ValueError("src, dst and w must be 1-D")
+    if not (src.numel() == dst.numel() == w.numel()):
+        raise ValueError("src, dst and w must have the same length")
+
+
+def ccm_weights_from_log(log_w, stream=None):
+    """w = exp(log_w) computed by the library (device float64 [m])."""
+    torch = _torch()
+    _f64(log_w)
+    w = torch.empty_like(log_w)
+    if log_w.numel():
+        _check(lib().ccm_weights_from_log(_ptr(log_w.contiguous()), log_w.numel(), _ptr(w),
+                                          _stream(stream)))
+    return w
 
 
 def ccm_version():
@@ -247,11 +278,19 @@ def ccm_solve_path(A, src, dst, w, gammas, q, tol, opts=None, want_U=False, want
     Returns a dict with X [T, n, d], U [T, m_canon, d] (if want_U), labels
     [T, n], n_clusters, kkt [T, 4] (R_D, R_C, R_U, eta), status, stats."""
     torch = _torch()
-    _f64(A)
+    _graph_args(A, src, dst, w)
     n, d = A.shape
     m = int(src.numel())
+    if X_warm is not None and (_f64(X_warm).shape != (n, d)):
+        raise ValueError("X_warm must be float64 [n, d]")
+    if U_warm is not None and (_f64(U_warm).dim() != 2 or U_warm.shape[1] != d):
+        raise ValueError("U_warm must be float64 [m_canon, d]")
     g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
     T = int(g.size)
+    if U_warm is not None:
+        mc = ccm_canonical_edge_count(src, dst, w, n, stream) if m else 0
+        if U_warm.shape[0] != mc:
+            raise ValueError(f"U_warm has {U_warm.shape[0]} rows, the canonical edges are {mc}")
     X = torch.empty((T, n, d), dtype=torch.float64, device=A.device)
     U = None
     if want_U:
@@ -388,9 +427,13 @@ def _make_ccm_solve():
 
         @staticmethod
         def forward(ctx, A, log_w, gamma, src, dst, tol=1e-11):
-            w = torch.exp(log_w).contiguous()
+            w = ccm_weights_from_log(log_w.contiguous())
             g = float(gamma)
             out = ccm_solve_path(A.contiguous(), src, dst, w, [g], 2.0, tol)
+            if int(out["status"][0]) != CCM_CONVERGED:
+                raise CcmError(CCM_E_NOT_CONVERGED,
+                               f"forward solve stopped with status {int(out['status'][0])} at "
+                               f"KKT {float(np.max(out['kkt'][0][:3])):.3g} (tol {tol})")
             X = out["X"][0]
             labels = out["labels"][0]
             ctx.save_for_backward(A, w, X, labels, src, dst)
@@ -431,6 +474,8 @@ def ccm_solve_path_batched(instances, gammas, tol, opts=None, stream=None):
     N = len(instances)
     desc = (CcmInstance * max(N, 1))()
     a_off = e_off = x_off = l_off = 0
+    for inst in instances:
+        _graph_args(inst["A"], inst["src"], inst["dst"], inst["w"])
     for i, inst in enumerate(instances):
         n, d = inst["A"].shape
         m = int(inst["src"].numel())

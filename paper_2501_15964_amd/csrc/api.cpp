@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -174,6 +175,7 @@ const char* ccm_status_string(ccm_status s) {
         case CCM_E_HIP: return "HIP runtime error";
         case CCM_E_NOMEM: return "out of device memory";
         case CCM_E_CAPACITY: return "output capacity too small";
+        case CCM_E_NOT_CONVERGED: return "iterative solve did not converge";
         default: return "unknown status";
     }
 }
@@ -643,6 +645,15 @@ ccm_status ccm_labels(const double* A, const double* X, int64_t n, int64_t d,
     HIPCHK_API(hipMemcpyAsync(&h, nc.p, 4, hipMemcpyDeviceToHost, stream));
     HIPCHK_API(hipStreamSynchronize(stream));
     if (n_clusters_host) *n_clusters_host = h;
+    return CCM_OK;
+}
+
+ccm_status ccm_weights_from_log(const double* log_w, int64_t m, double* w, hipStream_t stream) {
+    g_err.clear();
+    if (m < 0) return fail(CCM_E_INVALID, "m < 0");
+    if (m > 0 && (!log_w || !w)) return fail(CCM_E_INVALID, "null argument");
+    if (m > 0) launch_exp(log_w, m, w, stream);
+    HIPCHK_API(hipGetLastError());
     return CCM_OK;
 }
 

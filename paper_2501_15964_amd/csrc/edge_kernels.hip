@@ -318,12 +318,16 @@ __global__ __launch_bounds__(kBlock) void k_fused_flags(int64_t m, int d,
                                                         const int* __restrict__ src,
                                                         const int* __restrict__ dst,
                                                         const double* __restrict__ X, double thr,
+                                                        const double* __restrict__ spread,
+                                                        const double* __restrict__ vthr,
                                                         int* __restrict__ fused) {
+    if (spread) thr = 1e-5 * (1.0 + spread[0]);
     const int gl = (threadIdx.x & 63) % LPR;
     constexpr int GPB = kBlock / LPR;
     for (int64_t l = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; l < m;
          l += int64_t(gridDim.x) * GPB) {
         const int64_t i = src[l], j = dst[l];
+        const double th = vthr ? vthr[i] : thr;
         double s = 0.0;
 #pragma unroll
         for (int t = 0; t < NPER; ++t) {
@@ -334,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_flags(int64_t m, int d,
             }
         }
         s = group_sum<LPR>(s);
-        if (gl == 0) fused[l] = sqrt(s) <= thr ? 1 : 0;
+        if (gl == 0) fused[l] = sqrt(s) <= th ? 1 : 0;
     }
 }
 
@@ -425,11 +429,11 @@ void launch_project(int64_t m, int d, int qk, const double* Y, const double* w, 
 }
 
 void launch_fused_flags(const DevGraph& g, int d, const double* X, double thr, int* fused,
-                        hipStream_t s) {
+                        hipStream_t s, const double* spread, const double* vthr) {
     dispatch_row(d, [&](auto L, auto N) {
         constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
         hipLaunchKernelGGL((k_fused_flags<lpr, nper>), dim3(row_grid(g.m, lpr)), dim3(kBlock), 0,
-                           s, g.m, d, g.src, g.dst, X, thr, fused);
+                           s, g.m, d, g.src, g.dst, X, thr, spread, vthr, fused);
     });
 }
 

@@ -167,9 +167,12 @@ int launch_edge_ama(const DevGraph& g, int d, int qk, double gamma, double nu, d
 void launch_gather(const DevGraph& g, int d, const double* X, double* Y, hipStream_t s);
 void launch_project(int64_t m, int d, int qk, const double* Y, const double* w, double gamma,
                     bool prox, double* out, hipStream_t s);
-// fused[l] = ||x_src - x_dst||_2 <= thr
+// fused[l] = ||x_src - x_dst||_2 <= thr; with `spread` (a device scalar S)
+// the threshold is 1e-5 (1 + S) instead of thr; with `vthr` (per vertex) it is
+// vthr[src_l]
 void launch_fused_flags(const DevGraph& g, int d, const double* X, double thr, int* fused,
-                        hipStream_t s);
+                        hipStream_t s, const double* spread = nullptr,
+                        const double* vthr = nullptr);
 
 // ---- vertex kernels (vertex_kernels.hip) ----------------------------------
 // out = cx X + ca A + cz B^T Z (X or A may be null).  With `diag` (SSNAL),
@@ -246,6 +249,8 @@ struct FinalizeJobs {
 };
 void launch_finalize_multi(const FinalizeJobs& jobs, int njobs, hipStream_t s);
 void launch_fill(double* x, int64_t N, double v, hipStream_t s);
+// y = exp(x), elementwise
+void launch_exp(const double* x, int64_t n, double* y, hipStream_t s);
 // flag[0] = 1 if some x[k] (k < count) is NaN or infinite; flag[0] is not cleared
 void launch_flag_nonfinite(const double* x, int64_t count, int* flag, hipStream_t s);
 // x += alpha y
@@ -265,6 +270,13 @@ void launch_lap_dinv(const DevGraph& g, int d, double c0, double sigma, double* 
 // S = max_i ||a_i - mean||; result written to out[0].
 void launch_spread(const double* A, int64_t n, int d, double* work, double* out, hipStream_t s);
 int spread_work_size(int64_t n, int d);
+// per vertex: the fusion threshold 1e-5 (1 + S_s) of its segment s, with
+// S_s the spread of the segment's rows of A computed exactly as
+// launch_spread computes it for those rows alone.  work: doubles of
+// seg_threshold_work_size(nseg, d).
+void launch_seg_thresholds(const double* A, const int64_t* seg, int nseg, int d, double* work,
+                           double* vthr, hipStream_t s);
+int seg_threshold_work_size(int nseg, int d);
 void launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 // batched solves: copy union rows (and labels, offset to start at 0 per
 // instance) into per-instance output blocks: instance s owns rows

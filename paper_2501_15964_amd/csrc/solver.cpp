@@ -212,7 +212,7 @@ struct Solver::Impl {
     double floor_scale = 1.0;               // inner gradient floor relative to tol
     std::vector<double> nA_inst;            // ||A|| per segment
     std::vector<std::array<double, 7>> inst_res;
-    DevMem vrows, erows, vsum, esum;
+    DevMem vrows, erows, vsum, esum, vthr;
 
     Impl(const DevGraph& graph, int d_, int qk_, const double* A_, hipStream_t s_,
          const ccm_options& opt, double tol_, std::string& e)
@@ -1034,7 +1034,10 @@ struct Solver::Impl {
     ccm_status labels(int* lab_out, int* nclus_host) {
         Timed t(prof, CCM_K_OTHER);
         const double thr = 1e-5 * (1.0 + spread);
-        if (m > 0) launch_fused_flags(g, d, X, thr, fused.as<int>(), s);
+        // batched: each instance's own threshold (from its own spread)
+        if (m > 0)
+            launch_fused_flags(g, d, X, thr, fused.as<int>(), s, nullptr,
+                               batch ? vthr.as<double>() : nullptr);
         int* lab = lab_out;
         DevMem scratch;
         if (!lab) {
@@ -1141,6 +1144,15 @@ ccm_status Solver::run_batched(const double* gammas, int T, const BatchSpec& b) 
             mn = std::min(mn, I.nA_inst[i]);
         }
         I.floor_scale = (1.0 + mn) / (1.0 + I.nA);
+    }
+    // per-vertex fusion thresholds from each instance's own spread
+    {
+        DevMem work;
+        HIPCHK(work.alloc(size_t(seg_threshold_work_size(S, I.d)) * 8, I.s));
+        HIPCHK(I.vthr.alloc(size_t(I.n) * 8, I.s));
+        launch_seg_thresholds(I.A, b.vseg_dev, S, I.d, work.as<double>(), I.vthr.as<double>(),
+                              I.s);
+        HIPCHK(hipStreamSynchronize(I.s));
     }
     DevMem lab, firsts;
     HIPCHK(lab.alloc(size_t(I.n) * 4, I.s));

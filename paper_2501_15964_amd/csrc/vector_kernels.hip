@@ -291,6 +291,80 @@ __global__ __launch_bounds__(kBlock) void k_max_sqrt(const double* __restrict__ 
     }
 }
 
+// The same three steps per segment of rows [seg[s], seg[s + 1]) (blockIdx.y
+// = s), with the same row chunks and summation order as for a matrix of the
+// segment's rows alone, so each segment's S is bit-identical to its own.
+__global__ __launch_bounds__(kBlock) void k_colsum_seg(const double* __restrict__ A,
+                                                       const int64_t* __restrict__ seg, int d,
+                                                       double* __restrict__ part) {
+    const int64_t a = seg[blockIdx.y], n = seg[blockIdx.y + 1] - a;
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = int64_t(blockIdx.x) * per;
+    const int64_t r1 = r0 + per < n ? r0 + per : n;
+    double* out = part + (int64_t(blockIdx.y) * gridDim.x + blockIdx.x) * d;
+    for (int k = threadIdx.x; k < d; k += blockDim.x) {
+        double t = 0.0;
+        for (int64_t i = r0; i < r1; ++i) t += A[(a + i) * d + k];
+        out[k] = t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_colmean_seg(const double* __restrict__ part,
+                                                        int nparts,
+                                                        const int64_t* __restrict__ seg, int d,
+                                                        double* __restrict__ mean) {
+    const int64_t n = seg[blockIdx.y + 1] - seg[blockIdx.y];
+    const double* p0 = part + int64_t(blockIdx.y) * nparts * d;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d; k += gridDim.x * blockDim.x) {
+        double t = 0.0;
+        for (int p = 0; p < nparts; ++p) t += p0[int64_t(p) * d + k];
+        mean[int64_t(blockIdx.y) * d + k] = t / double(n);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rowdev_max_seg(const double* __restrict__ A,
+                                                           const int64_t* __restrict__ seg, int d,
+                                                           const double* __restrict__ mean,
+                                                           double* __restrict__ bmax) {
+    const int64_t a = seg[blockIdx.y], n = seg[blockIdx.y + 1] - a;
+    const double* mu = mean + int64_t(blockIdx.y) * d;
+    double best = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * kBlock) {
+        double t = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double e = A[(a + i) * d + k] - mu[k];
+            t += e * e;
+        }
+        best = fmax(best, t);
+    }
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = best;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bmax[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+}
+
+// per vertex of segment s: thr = 1e-5 (1 + S_s), S_s = sqrt(max of the
+// segment's nb block maxima)
+__global__ __launch_bounds__(kBlock) void k_seg_thresholds(const double* __restrict__ bmax, int nb,
+                                                           const int64_t* __restrict__ seg,
+                                                           double* __restrict__ vthr) {
+    __shared__ double S;
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int b = 0; b < nb; ++b) t = fmax(t, bmax[int64_t(blockIdx.x) * nb + b]);
+        S = sqrt(t);
+    }
+    __syncthreads();
+    const double thr = 1e-5 * (1.0 + S);
+    for (int64_t i = seg[blockIdx.x] + threadIdx.x; i < seg[blockIdx.x + 1]; i += kBlock)
+        vthr[i] = thr;
+}
+
 // 16-byte elements, four independent loads in flight per thread
 __global__ __launch_bounds__(kBlock) void k_stream_copy(const uint4* __restrict__ a,
                                                         uint4* __restrict__ b, int64_t N) {
@@ -499,6 +573,37 @@ void launch_spread(const double* A, int64_t n, int d, double* work, double* out,
                        kSpreadBlocks, n, d, mean);
     hipLaunchKernelGGL(k_rowdev_max, dim3(kSpreadBlocks), dim3(kBlock), 0, s, A, n, d, mean, bmax);
     hipLaunchKernelGGL(k_max_sqrt, dim3(1), dim3(kBlock), 0, s, bmax, kSpreadBlocks, out);
+}
+
+__global__ __launch_bounds__(kBlock) void k_exp(const double* __restrict__ x, int64_t n,
+                                                double* __restrict__ y) {
+    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n;
+         k += int64_t(gridDim.x) * kBlock)
+        y[k] = exp(x[k]);
+}
+
+void launch_exp(const double* x, int64_t n, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_exp, dim3(flat_grid(n)), dim3(kBlock), 0, s, x, n, y);
+}
+
+int seg_threshold_work_size(int nseg, int d) {
+    return nseg * (kSpreadBlocks * d + d + kSpreadBlocks);
+}
+
+void launch_seg_thresholds(const double* A, const int64_t* seg, int nseg, int d, double* work,
+                           double* vthr, hipStream_t s) {
+    if (nseg < 1) return;
+    double* part = work;
+    double* mean = part + int64_t(nseg) * kSpreadBlocks * d;
+    double* bmax = mean + int64_t(nseg) * d;
+    hipLaunchKernelGGL(k_colsum_seg, dim3(kSpreadBlocks, nseg), dim3(kBlock), 0, s, A, seg, d,
+                       part);
+    hipLaunchKernelGGL(k_colmean_seg, dim3((d + kBlock - 1) / kBlock, nseg), dim3(kBlock), 0, s,
+                       part, kSpreadBlocks, seg, d, mean);
+    hipLaunchKernelGGL(k_rowdev_max_seg, dim3(kSpreadBlocks, nseg), dim3(kBlock), 0, s, A, seg, d,
+                       mean, bmax);
+    hipLaunchKernelGGL(k_seg_thresholds, dim3(nseg), dim3(kBlock), 0, s, bmax, kSpreadBlocks, seg,
+                       vthr);
 }
 
 void launch_segsum(const double* rows, int nv, const int64_t* seg, int nseg, double* out,

@@ -11,6 +11,8 @@
 // dL/dlog w_l = -gamma w_l <lambda_ci - lambda_cj, ghat_l>, and
 // dL/dgamma = -sum_l w_l <lambda_ci - lambda_cj, ghat_l>.
 #include <algorithm>
+#include <cmath>
+#include <string>
 #include "vjp.hpp"
 
 #include <cmath>
@@ -131,6 +133,10 @@ ccm_status path_vjp(const double* A, int64_t n, int d, const int* src, const int
             rz = rz2;
         }
         if (iters_out) *iters_out = it;
+        // a CG that stopped short of the tolerance (iteration cap or a
+        // breakdown) still writes the gradients of its last iterate, but the
+        // call reports it
+        const bool short_stop = bb > 0 && !(rr <= thr);
         // gradients
         launch_expand(n, d, labels, x.as<double>(), dLdA, s);
         DevMem dlw;
@@ -150,6 +156,12 @@ ccm_status path_vjp(const double* A, int64_t n, int d, const int* src, const int
         if (m > 0) dg = -hs[0];
         if (dLdgamma) *dLdgamma = dg;
         HIPCHK(hipGetLastError());
+        if (short_stop) {
+            err = "adjoint CG stopped after " + std::to_string(it) +
+                  " iterations above its tolerance (relative residual " +
+                  std::to_string(std::sqrt(rr / bb)) + ")";
+            return CCM_E_NOT_CONVERGED;
+        }
     }
     return CCM_OK;
 }

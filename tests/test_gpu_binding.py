@@ -1,0 +1,56 @@
+"""Status reporting and per-instance thresholds through the C ABI (GPU)."""
+import numpy as np
+import pytest
+
+import oracle
+import synthdata
+from gpu_util import need_gpu, dev, host, graph_dev
+from test_gpu_solver import _adjoint_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def test_vjp_reports_an_unconverged_cg():
+    torch, ccm = need_gpu()
+    from paper_2501_15964_amd.ccm import CcmError
+    A, src, dst, w, T = _adjoint_problem()
+    g = 0.15
+    out = ccm.ccm_solve_path(dev(A), *graph_dev(src, dst, w), [g], 2.0, 1e-11)
+    X = out["X"][0]
+    G = dev(2 * (host(X) - T))
+    with pytest.raises(CcmError) as ex:
+        ccm.ccm_path_vjp(dev(A), *graph_dev(src, dst, w), g, X, out["labels"][0], G,
+                         tol=1e-13, max_iter=1)
+    assert ex.value.status == ccm.CCM_E_NOT_CONVERGED
+    # the same call with room to converge succeeds
+    ccm.ccm_path_vjp(dev(A), *graph_dev(src, dst, w), g, X, out["labels"][0], G, tol=1e-13)
+
+
+def test_weights_from_log_match_exp():
+    torch, ccm = need_gpu()
+    lw = np.random.default_rng(4001).normal(scale=20.0, size=1001)
+    w = host(ccm.ccm_weights_from_log(dev(lw)))
+    np.testing.assert_array_max_ulp(w, np.exp(lw), maxulp=1)
+
+
+def test_batched_labels_use_each_instance_scale():
+    # two instances of one (q, d) group at scales 1e-3 and 1e3: a fusion
+    # threshold from the union's spread would fuse every edge of the small
+    # one; labels must equal each instance's own ccm_solve_path labels
+    torch, ccm = need_gpu()
+    insts = []
+    for scale, seed in ((1e-3, 4002), (1e3, 4003)):
+        A, _ = synthdata.mixture64(n_per=30, d=4, n_blobs=3, seed=seed)
+        A = A * scale
+        src, dst, w, *_ = oracle.knn_graph(A, 5, None)
+        insts.append(dict(A=dev(A), src=dev(src.astype(np.int32)),
+                          dst=dev(dst.astype(np.int32)), w=dev(w), q=2.0))
+    gammas = [1e-6, 1e-5]
+    res = ccm.ccm_solve_path_batched(insts, gammas, 1e-8)
+    for k, it in enumerate(insts):
+        single = ccm.ccm_solve_path(it["A"], it["src"], it["dst"], it["w"], gammas, 2.0, 1e-8)
+        for t in range(len(gammas)):
+            assert res[k]["status"][t] == 0
+            assert np.array_equal(host(res[k]["labels"][t]), host(single["labels"][t])), (k, t)
+            assert res[k]["n_clusters"][t] == single["n_clusters"][t]
+    assert res[0]["n_clusters"][0] > 1
