@@ -332,6 +332,24 @@ ccm_status ccm_labels(const double* A, const double* X, int64_t n, int64_t d,
                       const int32_t* src, const int32_t* dst, int64_t m, int32_t* labels,
                       int32_t* n_clusters_host, hipStream_t stream);
 
+/* ccm_labels for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same labels and count as ccm_labels, but every temporary (spread partials,
+ * fused-edge flags, union-find parents, scan buffers) lives in one fixed
+ * 32 MiB device array that the library holds on each device it runs on until
+ * the process ends; the call allocates and frees nothing.  Capacity: the
+ * buffers need about 4 m + 8 n bytes plus 1 KiB per feature, so for example
+ * n = 1e6, m = 4e6, d <= 1024 fits; larger problems return CCM_E_CAPACITY
+ * before anything is launched (also when n > 2^22 or m > 2^23).  All calls on
+ * one device share the array and it keeps the last call's contents (every
+ * buffer is written before it is read): calls that overlap on one device,
+ * on any streams or threads, race and must be serialised by the caller.
+ * The caller passes inputs and outputs as for ccm_labels.  Synchronises
+ * `stream` (to return n_clusters_host). */
+ccm_status ccm_labels_noalloc(const double* A, const double* X, int64_t n, int64_t d,
+                              const int32_t* src, const int32_t* dst, int64_t m, int32_t* labels,
+                              int32_t* n_clusters_host, hipStream_t stream);
+
 /* Plain device copy of `bytes` bytes with the library's streaming kernel
  * (calibration of achievable HBM bandwidth).  *ms_host: average duration of
  * one launch over `repeats` launches, from HIP events. */

@@ -22,7 +22,7 @@ __all__ = [
     "ccm_canonical_edge_count", "ccm_op_gather", "ccm_op_project", "ccm_op_prox",
     "ccm_op_scatter", "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy",
     "ccm_path_vjp", "CCMSolve", "ccm_solve_path_batched", "CcmInstance", "EXPORTED_SYMBOLS",
-    "ccm_build_knn_graph_u8", "ccm_release_workspace",
+    "ccm_build_knn_graph_u8", "ccm_release_workspace", "ccm_labels_noalloc",
     "ccm_weights_from_log", "CCM_E_NOT_CONVERGED",
 ]
 
@@ -41,7 +41,7 @@ EXPORTED_SYMBOLS = [
     "ccm_op_gather", "ccm_op_project", "ccm_op_prox", "ccm_op_scatter",
     "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy", "ccm_path_vjp",
     "ccm_solve_path_batched", "ccm_build_knn_graph_u8", "ccm_release_workspace",
-    "ccm_weights_from_log",
+    "ccm_labels_noalloc", "ccm_weights_from_log",
 ]
 
 
@@ -122,6 +122,7 @@ def lib():
         "ccm_op_hess_matvec": [P, P, I64, I64, P, P, P, I64, F64, F64, F64, P, P, I32, P, P],
         "ccm_kkt": [P, P, P, I64, I64, P, P, P, I64, F64, F64, P, P],
         "ccm_labels": [P, P, I64, I64, P, P, I64, P, P, P],
+        "ccm_labels_noalloc": [P, P, I64, I64, P, P, I64, P, P, P],
         "ccm_weights_from_log": [P, I64, P, P],
         "ccm_stream_copy": [P, P, I64, I32, P, P],
         "ccm_path_vjp": [P, I64, I64, P, P, P, I64, F64, F64, P, P, P, P, P, P, F64, I32, P, P],
@@ -384,6 +385,22 @@ def ccm_labels(A, X, src, dst, stream=None):
     nc = ctypes.c_int32(0)
     _check(lib().ccm_labels(_ptr(_f64(A)), _ptr(_f64(X)), n, d, _ptr(_i32(src)),
                             _ptr(_i32(dst)), m, _ptr(lab), ctypes.byref(nc), _stream(stream)))
+    return lab, nc.value
+
+
+def ccm_labels_noalloc(A, X, src, dst, labels=None, stream=None):
+    """ccm_labels with the library's fixed work space (no device allocation
+    inside the call); `labels` (device int32 [n]) may be given by the caller."""
+    torch = _torch()
+    n, d = A.shape
+    m = src.numel()
+    lab = labels if labels is not None else torch.empty(n, dtype=torch.int32, device=A.device)
+    if lab.dtype != torch.int32 or lab.numel() != n or not lab.is_contiguous():
+        raise ValueError("labels must be a contiguous int32 tensor of n values")
+    nc = ctypes.c_int32(0)
+    _check(lib().ccm_labels_noalloc(_ptr(_f64(A)), _ptr(_f64(X)), n, d, _ptr(_i32(src)),
+                                    _ptr(_i32(dst)), m, _ptr(lab), ctypes.byref(nc),
+                                    _stream(stream)))
     return lab, nc.value
 
 

@@ -83,6 +83,62 @@ ccm_options defaults() {
     return o;
 }
 
+// ---- work space of the entry point that allocates nothing ---------------------
+// A fixed device array: each device that runs the library holds its own copy
+// until the process ends.  In host code `scratch` only names the symbol; its
+// device address (one per device) comes from hipGetSymbolAddress.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+constexpr int64_t kNoAllocMaxN = int64_t(1) << 22;
+constexpr int64_t kNoAllocMaxM = int64_t(1) << 23;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+ccm_status noalloc_scratch(unsigned char** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* ptr[kMaxDevices] = {};
+    int dev = 0;
+    HIPCHK_API(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(CCM_E_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(CCM_E_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                       hipGetErrorString(e));
+        ptr[dev] = p;
+    }
+    *out = static_cast<unsigned char*>(ptr[dev]);
+    return CCM_OK;
+}
+
+// byte offsets of ccm_labels_noalloc's buffers in the array (256-aligned)
+struct LabelsScratch {
+    size_t spread, S, nc, fused, parent, rank, temp, temp_bytes, total;
+};
+LabelsScratch labels_scratch(int64_t n, int d, int64_t m) {
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    LabelsScratch L{};
+    size_t at = 0;
+    L.spread = at;
+    at += up(size_t(spread_work_size(n, d)) * 8);
+    L.S = at;
+    at += up(8);
+    L.nc = at;
+    at += up(4);
+    L.fused = at;
+    at += up(size_t(std::max<int64_t>(m, 1)) * 4);
+    L.parent = at;
+    at += up(size_t(n) * 4);
+    L.rank = at;
+    at += up(size_t(n + 1) * 4);
+    L.temp = at;
+    L.temp_bytes = labels_temp_bytes(n);
+    at += up(L.temp_bytes);
+    L.total = at;
+    return L;
+}
+
 // concurrent (q, d) groups of ccm_solve_path_batched
 constexpr int kBatchedStreams = 4;
 
@@ -643,6 +699,49 @@ ccm_status ccm_labels(const double* A, const double* X, int64_t n, int64_t d,
                   labels, nc.as<int>(), stream);
     int h = 0;
     HIPCHK_API(hipMemcpyAsync(&h, nc.p, 4, hipMemcpyDeviceToHost, stream));
+    HIPCHK_API(hipStreamSynchronize(stream));
+    if (n_clusters_host) *n_clusters_host = h;
+    return CCM_OK;
+}
+
+ccm_status ccm_labels_noalloc(const double* A, const double* X, int64_t n, int64_t d,
+                              const int32_t* src, const int32_t* dst, int64_t m, int32_t* labels,
+                              int32_t* n_clusters_host, hipStream_t stream) {
+    g_err.clear();
+    ccm_status st = check_dims(n, d);
+    if (st != CCM_OK) return st;
+    if (m < 0) return fail(CCM_E_INVALID, "m < 0");
+    if (n > kNoAllocMaxN || m > kNoAllocMaxM)
+        return fail(CCM_E_CAPACITY, "ccm_labels_noalloc: n or m above its fixed work space (n <= " +
+                                        std::to_string(kNoAllocMaxN) + ", m <= " +
+                                        std::to_string(kNoAllocMaxM) + ")");
+    const LabelsScratch L = labels_scratch(n, int(d), m);
+    if (L.total > kNoAllocScratchBytes)
+        return fail(CCM_E_CAPACITY, "ccm_labels_noalloc: problem needs " + std::to_string(L.total) +
+                                        " bytes of work space, the fixed array holds " +
+                                        std::to_string(kNoAllocScratchBytes));
+    unsigned char* base = nullptr;
+    st = noalloc_scratch(&base);
+    if (st != CCM_OK) return st;
+    double* work = reinterpret_cast<double*>(base + L.spread);
+    double* S = reinterpret_cast<double*>(base + L.S);
+    int* nc = reinterpret_cast<int*>(base + L.nc);
+    int* fused = reinterpret_cast<int*>(base + L.fused);
+    int* parent = reinterpret_cast<int*>(base + L.parent);
+    int* rank = reinterpret_cast<int*>(base + L.rank);
+    void* temp = base + L.temp;
+    DevGraph g;
+    g.n = n;
+    g.m = m;
+    g.src = src;
+    g.dst = dst;
+    // the same kernels as ccm_labels; the spread S stays on the device
+    launch_spread(A, n, int(d), work, S, stream);
+    if (m > 0) launch_fused_flags(g, int(d), X, 0.0, fused, stream, S);
+    launch_labels(n, m, src, dst, fused, parent, rank, temp, L.temp_bytes, labels, nc, stream);
+    HIPCHK_API(hipGetLastError());
+    int h = 0;
+    HIPCHK_API(hipMemcpyAsync(&h, nc, 4, hipMemcpyDeviceToHost, stream));
     HIPCHK_API(hipStreamSynchronize(stream));
     if (n_clusters_host) *n_clusters_host = h;
     return CCM_OK;
