@@ -2,25 +2,30 @@
 """Benchmark: one clustering path of the convex clustering model on one MI355X.
 
 A step is one pass of the whole hot path over one batch of synthetic input
-already resident in HBM: the exact k-NN Gaussian weight graph
-(ccm_build_knn_graph) followed by the warm-started SSNAL path over the gamma
-grid to relative KKT <= 1e-6 (ccm_solve_path: edge gather, per-edge
-projection, atomic-free B^T scatter, Newton-CG matvecs, line search, KKT
-tests, cluster labels).  The reported value is the wall time of that step.
+already resident in HBM: the exact k-NN Gaussian weight graph followed by the
+warm-started SSNAL path over the gamma grid to relative KKT <= 1e-6
+(ccm_solve_path: edge gather, per-edge projection, atomic-free B^T scatter,
+Newton-CG matvecs, line search, KKT tests, cluster labels).  The reported
+value is the wall time of that step.
 
-Default workload: n = 10,000 points in d = 64 drawn from 10 Gaussians
-(sigma 1, centres N(0, 25 I)), k = 10, phi = 1 / median k-NN distance,
-q = 2, 20 gammas log-spaced in [1e-3, 1e2].
+Default workload (the largest single-GPU configuration): n = 100,000 points
+in d = 784 from 10 image-shaped classes (prototypes U[0,1], pixel noise
+N(0, 0.1^2), clipped and quantised to k/255), k = 10 graph from the exact
+integer distances of the 8-bit codes (int8 matrix cores), phi = 1 / median
+k-NN distance, q = 2, 15 gammas log-spaced in [1e-3, 1e1].
+
+Beside the headline the same JSON line reports: the same path for q = 1 and
+q = inf ("q_legs"); the n = 10,000, d = 64 mixture path and the n = 200
+two-dimensional blobs, each by SSNAL and by ADMM ("workloads"); the adjoint
+(n = 20000, d = 32: tight forward solve + VJP) and the batched form (512
+instances of uneven n, d and q, 10 gammas each, one call).
 
 The roofline object reports the Newton/CG matvec (the dominant kernel):
 algorithmic bytes of the launches that did work in the timed steps divided
 by their summed HIP-event durations (recorded by the library on its launch
-stream).  The cpu_baseline object times the oracle (CPU, FP64) on a bounded
-sample of the same workload and scales it to one path.
-
-The same JSON line also reports the growth forms beside the plain path:
-"adjoint" (n = 20000, d = 32: tight forward solve + VJP) and "batched" (512
-instances of uneven n, d and q, 10 gammas each, one batched call).
+stream).  The cpu_baseline object times the CPU oracle on a bounded sample
+of the same workload and prices one step with the GPU run's operation
+counts.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -93,11 +98,95 @@ def traffic_record(kernel_key):
     return rec
 
 
-def cpu_baseline(A_np, K_np, wl, graph, budget_s=20.0):
-    """The oracle on a bounded sample: k-NN rows and an evenly spaced subset
-    of the gammas (each warm-started from the previous sampled gamma), scaled
-    to one full step.  The solve sample runs on `graph` (the step's own graph,
-    copied to the host; building it is not part of the sample)."""
+def _counts(out):
+    st = out["stats"]
+    return {k: int(sum(s[k] for s in st)) for k in ("outer", "newton", "cg", "linesearch")}
+
+
+def cpu_baseline_sampled(A_np, K_np, wl, graph, counts):
+    """The oracle on a bounded sample of a large step, priced with the GPU
+    run's operation counts.
+
+    A whole oracle path at n = 1e5, d = 784 takes hours, so the sample times
+    the oracle's own pieces: the k-NN of 8 query rows (scaled by n / 8), and
+    the three operations an oracle SSNAL iteration is made of
+    (ssnal_evaluate: edge pass + projection + gradient; ssnal_hessian_apply:
+    one Newton matvec; kkt_residuals: the stopping test) at the full n on the
+    first m/16 and the first m/8 of the step's edges, fitted as a + b m and
+    extrapolated to all m edges.  One step = k-NN + (outer + line-search
+    trials) x evaluate + CG iterations x matvec + outer x KKT, with the
+    counts of the GPU path (the oracle's own counts differ by its penalty
+    heuristic)."""
+    import oracle
+    from oracle import solvers as osv
+    from oracle import operators as ops
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(1)
+    except Exception:
+        lim = None
+    n, d = A_np.shape
+    k = wl["k"]
+    rows = np.arange(0, n, n // 8)[:8]
+    t0 = time.perf_counter()
+    if K_np is not None:
+        oracle.knn_brute_u8(K_np, k, rows=rows, block=1)
+    else:
+        oracle.knn_brute(A_np, k, rows=rows)
+    t_knn_s = time.perf_counter() - t0
+    t_knn = t_knn_s * n / len(rows)
+    src, dst, w = graph
+    m = len(src)
+    gamma0 = 10.0 ** wl["gammas"][0]
+    sizes = [m // 16, m // 8]
+    times = {"evaluate": [], "hessian": [], "kkt": []}
+    measured = t_knn_s
+    rng = np.random.default_rng(7)
+    nA = float(np.linalg.norm(A_np))
+    for ms in sizes:
+        B = ops.incidence(src[:ms], dst[:ms], n)
+        Bt = B.T.tocsr()
+        r = gamma0 * w[:ms]
+        U = np.zeros((ms, d))
+        t0 = time.perf_counter()
+        ev = osv.ssnal_evaluate(A_np, U, 1.0, A_np, B, Bt, r, wl["q"], nA)
+        t1 = time.perf_counter()
+        V = rng.normal(size=A_np.shape)
+        osv.ssnal_hessian_apply(V, ev["Y"], 1.0, B, Bt, r, wl["q"])
+        t2 = time.perf_counter()
+        del ev, V
+        ops.kkt_residuals(A_np, U, A_np, B, r, wl["q"])
+        t3 = time.perf_counter()
+        times["evaluate"].append(t1 - t0)
+        times["hessian"].append(t2 - t1)
+        times["kkt"].append(t3 - t2)
+        measured += t3 - t0
+        del U, B, Bt
+    fits = {}
+    for key, tv in times.items():
+        b = (tv[1] - tv[0]) / (sizes[1] - sizes[0])
+        fits[key] = max(tv[0] + b * (m - sizes[0]), tv[1])
+    n_eval = counts["outer"] + counts["linesearch"]
+    value = (t_knn + n_eval * fits["evaluate"] + counts["cg"] * fits["hessian"]
+             + counts["outer"] * fits["kkt"])
+    if lim is not None and hasattr(lim, "unregister"):
+        lim.unregister()
+    return dict(value=round(value, 1), unit="s", cores=1, kind="oracle",
+                host_cores=os.cpu_count(),
+                sample=(f"oracle k-NN of 8 of {n} query rows (x{n // 8}); oracle ssnal_evaluate, "
+                        f"ssnal_hessian_apply and kkt_residuals at n={n}, d={d} on the first "
+                        f"{sizes[0]} and {sizes[1]} of {m} edges, fitted linearly in m and "
+                        f"extrapolated; one step = k-NN + {n_eval} evaluations + "
+                        f"{counts['cg']} matvecs + {counts['outer']} KKT tests (the GPU path's "
+                        f"counts); single thread"),
+                per_op_s={kk: round(v, 3) for kk, v in fits.items()},
+                knn_s=round(t_knn, 2), measured_s=round(measured, 2))
+
+
+def cpu_baseline_solved(A_np, K_np, wl, graph, budget_s=20.0):
+    """The oracle on a bounded sample of a small step: k-NN rows and an
+    evenly spaced subset of the gammas (each warm-started from the previous
+    sampled gamma), scaled to one full step."""
     import oracle
     try:
         from threadpoolctl import threadpool_limits
@@ -106,7 +195,6 @@ def cpu_baseline(A_np, K_np, wl, graph, budget_s=20.0):
         lim = None
     n = A_np.shape[0]
     k = wl["k"]
-    # k-NN: a sample of query rows, scaled by n / rows
     nrows = 200 if n * A_np.shape[1] <= 2e7 else 8
     rows = np.arange(0, n, max(1, n // nrows))
     t0 = time.perf_counter()
@@ -132,9 +220,10 @@ def cpu_baseline(A_np, K_np, wl, graph, budget_s=20.0):
             break
     per_gamma = t_solve / max(done, 1)
     value = t_knn + per_gamma * cnt
-    if lim is not None:
-        lim.unregister() if hasattr(lim, "unregister") else None
+    if lim is not None and hasattr(lim, "unregister"):
+        lim.unregister()
     return dict(value=round(value, 3), unit="s", cores=1, kind="oracle",
+                host_cores=os.cpu_count(),
                 sample=(f"oracle k-NN on {len(rows)} of {n} query rows (x{n/len(rows):.0f}) + "
                         f"SSNAL on {done} of {cnt} gammas (every {stride}th, warm-started from "
                         f"the previous sampled gamma; mean per gamma x{cnt}); single thread"),
@@ -206,15 +295,74 @@ def adjoint_leg(ccm, torch):
             "dL_dgamma": dg}
 
 
+def path_summary(out, seconds):
+    return {"seconds": round(seconds, 4), "max_kkt": float(np.max(out["kkt"][:, :3])),
+            "status": [int(v) for v in out["status"]],
+            "n_clusters": [int(c) for c in out["n_clusters"]],
+            "iterations": _counts(out)}
+
+
+def q_leg(ccm, torch, A, graph, wl, q):
+    """The headline workload's path for another q on the same graph (one run;
+    matvec launches sampled with HIP events as in the headline)."""
+    lo, hi, cnt = wl["gammas"]
+    gammas = np.logspace(lo, hi, int(cnt))
+    src, dst, w = graph
+    o = ccm.ccm_default_options(profile=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = ccm.ccm_solve_path(A, src, dst, w, gammas, q, wl["tol"], opts=o)
+    torch.cuda.synchronize()
+    rec = path_summary(out, time.perf_counter() - t0)
+    mv_ms = sum(s["kern_ms"][2] for s in out["stats"])
+    mv_calls = sum(s["kern_calls"][2] for s in out["stats"])
+    mv_bytes = sum(s["matvec_bytes"] for s in out["stats"])
+    if mv_ms > 0 and mv_calls > 0:
+        avg_s = mv_ms / 1000.0 / mv_calls
+        rec["matvec"] = {"avg_launch_us": round(avg_s * 1e6, 2), "launches": int(mv_calls),
+                         "algorithmic_bytes_per_launch": round(mv_bytes / mv_calls),
+                         "achieved_gbs": round(mv_bytes / mv_calls / avg_s / 1e9, 1)}
+    return rec
+
+
+def small_workload_leg(ccm, torch, name, steps=3):
+    """A smaller configuration, k-NN + path per step, by SSNAL and by ADMM."""
+    wl = WORKLOADS[name]
+    A_np, _ = make_points(wl)
+    A = torch.from_numpy(A_np).cuda()
+    lo, hi, cnt = wl["gammas"]
+    gammas = np.logspace(lo, hi, int(cnt))
+    rec = {"desc": wl["desc"], "n": int(A_np.shape[0]), "d": int(A_np.shape[1])}
+    for method, code in (("ssnal", 0), ("admm", 1)):
+        o = ccm.ccm_default_options(method=code)
+
+        def one():
+            t0 = time.perf_counter()
+            src, dst, w, _ = ccm.ccm_build_knn_graph(A, wl["k"], wl["phi"])
+            out = ccm.ccm_solve_path(A, src, dst, w, gammas, wl["q"], wl["tol"], opts=o)
+            torch.cuda.synchronize()
+            return out, time.perf_counter() - t0, int(src.numel())
+
+        one()
+        runs = [one() for _ in range(steps)]
+        out, _, m = runs[-1]
+        rec[method] = path_summary(out, float(np.mean([r[1] for r in runs])))
+        rec["m"] = m
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mixture64_n10000", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="images784_n100000", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--no-q-legs", action="store_true", help="skip the q = 1 and q = inf legs")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the smaller-configuration legs (SSNAL and ADMM)")
     ap.add_argument("--batched-count", type=int, default=512)
     ap.add_argument("--batched-budget", type=float, default=90.0,
                     help="wall-clock budget (s) of each (q, d) group of the batched leg")
@@ -233,6 +381,7 @@ def main():
     import paper_2501_15964_amd as ccm
 
     wl = WORKLOADS[args.workload]
+    log(f"generating {args.workload} ...")
     A_np, K_np = make_points(wl)
     n, d = A_np.shape
     lo, hi, cnt = wl["gammas"]
@@ -299,24 +448,19 @@ def main():
             bytes_per_launch = mv_bytes / mv_calls
             achieved = bytes_per_launch / avg_s / 1e9
             rec = traffic_record(f"k_matvec_q2/{args.workload}")
-            roofline = {"bound": "hbm", "kernel": "k_matvec (Newton/CG matvec, q=2)",
+            roofline = {"bound": "hbm", "kernel": "k_matvec_win (Newton/CG matvec, q=2)",
                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(achieved / HBM_PEAK_GBS, 4),
                         "traffic": (rec["bytes_per_launch"] if rec else None),
                         "avg_launch_us": round(avg_s * 1e6, 2),
                         "launches": int(mv_calls),
                         "algorithmic_bytes_per_launch": round(bytes_per_launch)}
+            if rec:
+                roofline["traffic_gbs"] = round(rec["bytes_per_launch"] / avg_s / 1e9, 1)
         names = ["edge", "scatter", "matvec", "cg_update", "other"]
         kern = {names[c]: {"ms": round(float(cls_ms[c]), 3), "launches": int(cls_calls[c])}
                 for c in range(5)}
         kern["note"] = "one untimed step with every kernel class timed (HIP events)"
-
-    # achievable copy bandwidth of the same device (calibration, untimed)
-    buf_a = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
-    buf_b = torch.empty_like(buf_a)
-    ms_copy = ccm.ccm_stream_copy(buf_a, buf_b, buf_a.numel() * 8, repeats=10)
-    copy_gbs = 2 * buf_a.numel() * 8 / (ms_copy / 1e3) / 1e9
-    del buf_a, buf_b
 
     rec = {
         "metric": METRIC,
@@ -338,24 +482,41 @@ def main():
         "max_kkt": kkt_max,
         "status": status,
         "n_clusters": [int(c) for c in out["n_clusters"]],
-        "iterations": {"newton": int(sum(s["newton"] for s in out["stats"])),
-                       "cg": int(sum(s["cg"] for s in out["stats"])),
-                       "outer": int(sum(s["outer"] for s in out["stats"]))},
+        "iterations": _counts(out),
         "roofline": roofline,
         "kernels_per_step": kern,
-        "copy_kernel_gbs": round(copy_gbs, 1),
         "cpu_baseline": None,
     }
+    if not args.no_q_legs:
+        rec["q_legs"] = {}
+        for q, name in ((1.0, "q1"), (math.inf, "qinf")):
+            log(f"q leg {name} ...")
+            rec["q_legs"][name] = q_leg(ccm, torch, A, graph_dev, wl, q)
+    if not args.no_workloads:
+        rec["workloads"] = {}
+        for name in WORKLOADS:
+            if name not in (args.workload, "images784_n100000"):
+                log(f"workload leg {name} ...")
+                rec["workloads"][name] = small_workload_leg(ccm, torch, name)
     if not args.no_adjoint:
         log("adjoint leg ...")
         rec["adjoint"] = adjoint_leg(ccm, torch)
     if not args.no_batched:
         log("batched leg ...")
         rec["batched"] = batched_leg(ccm, torch, args.batched_count, args.batched_budget)
+    # achievable copy bandwidth of the same device (calibration, untimed)
+    buf_a = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+    buf_b = torch.empty_like(buf_a)
+    ms_copy = ccm.ccm_stream_copy(buf_a, buf_b, buf_a.numel() * 8, repeats=10)
+    rec["copy_kernel_gbs"] = round(2 * buf_a.numel() * 8 / (ms_copy / 1e3) / 1e9, 1)
+    del buf_a, buf_b
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
         graph = tuple(t.cpu().numpy() for t in graph_dev)
-        rec["cpu_baseline"] = cpu_baseline(A_np, K_np, wl, graph)
+        if n * d > 2e7:
+            rec["cpu_baseline"] = cpu_baseline_sampled(A_np, K_np, wl, graph, _counts(out))
+        else:
+            rec["cpu_baseline"] = cpu_baseline_solved(A_np, K_np, wl, graph)
     print(json.dumps(rec))
 
 

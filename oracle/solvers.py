@@ -132,6 +132,30 @@ def _pcg(apply_A, b, diag, rtol, maxit):
     return x, it
 
 
+def ssnal_evaluate(Xc, Uc, s, A, B, Bt, r, q, nA):
+    """SSNAL merit function at X for multiplier Uc and penalty s: the edge
+    pass Y = U + s BX, Pi = Pi_C(Y), the gradient G = X - A + B^T Pi, phi,
+    the gradient norm gn = ||G|| / (1 + ||A||) and the primal residual rp."""
+    BX = B @ Xc
+    Y = Uc + s * BX
+    Pi = project(Y, r, q)
+    G = Xc - A + Bt @ Pi
+    Dx = Xc - A
+    # with ||Y||^2 - ||Y - Pi||^2 = 2<Y, Pi> - ||Pi||^2 and Y = U + sigma BX,
+    # phi = 1/2||X - A||^2 + <BX, Pi> - ||Pi - U||^2/(2 sigma): the same
+    # value without two large terms that cancel
+    phi = (0.5 * float((Dx * Dx).sum()) + float((BX * Pi).sum())
+           - float(((Pi - Uc) ** 2).sum()) / (2.0 * s))
+    gn = np.linalg.norm(G) / (1.0 + nA)
+    rp = np.linalg.norm(Pi - Uc) / (s * (1.0 + np.linalg.norm(BX) + np.linalg.norm(Pi)))
+    return dict(Y=Y, Pi=Pi, G=G, phi=phi, gn=gn, rp=rp)
+
+
+def ssnal_hessian_apply(V, Y, s, B, Bt, r, q):
+    """The SSNAL Newton matrix applied to V: V + s B^T P B V, P in dPi_C(Y)."""
+    return V + s * (Bt @ jacobian_apply(Y, r, q, B @ V))
+
+
 def ssnal(A, src, dst, w, gamma, q, tol=1e-6, X0=None, U0=None, sigma=None,
           opts=None, callback=None):
     """Solve (CCM) at one gamma by SSNAL.  Returns (X, U, sigma, info)."""
@@ -157,19 +181,7 @@ def ssnal(A, src, dst, w, gamma, q, tol=1e-6, X0=None, U0=None, sigma=None,
     nA = np.linalg.norm(A)
 
     def evaluate(Xc, Uc, s):
-        BX = B @ Xc
-        Y = Uc + s * BX
-        Pi = project(Y, r, q)
-        G = Xc - A + Bt @ Pi
-        Dx = Xc - A
-        # with ||Y||^2 - ||Y - Pi||^2 = 2<Y, Pi> - ||Pi||^2 and Y = U + sigma BX,
-        # phi = 1/2||X - A||^2 + <BX, Pi> - ||Pi - U||^2/(2 sigma): the same
-        # value without two large terms that cancel
-        phi = (0.5 * float((Dx * Dx).sum()) + float((BX * Pi).sum())
-               - float(((Pi - Uc) ** 2).sum()) / (2.0 * s))
-        gn = np.linalg.norm(G) / (1.0 + nA)
-        rp = np.linalg.norm(Pi - Uc) / (s * (1.0 + np.linalg.norm(BX) + np.linalg.norm(Pi)))
-        return dict(Y=Y, Pi=Pi, G=G, phi=phi, gn=gn, rp=rp)
+        return ssnal_evaluate(Xc, Uc, s, A, B, Bt, r, q, nA)
 
     rp_prev = np.inf
     res = None
@@ -183,7 +195,7 @@ def ssnal(A, src, dst, w, gamma, q, tol=1e-6, X0=None, U0=None, sigma=None,
             diag = 1.0 + sig * _diag_BtPB(Y, r, q, B_abs, d)
 
             def hess(V, Y=Y):
-                return V + sig * (Bt @ jacobian_apply(Y, r, q, B @ V))
+                return ssnal_hessian_apply(V, Y, sig, B, Bt, r, q)
 
             rtol = min(0.1, ev["gn"] ** 0.2)
             D, it = _pcg(hess, -ev["G"], diag, rtol, o["cg_maxit"])

@@ -365,19 +365,25 @@ __global__ __launch_bounds__(kBlock) void k_seg_thresholds(const double* __restr
         vthr[i] = thr;
 }
 
-// 16-byte elements, four independent loads in flight per thread
-__global__ __launch_bounds__(kBlock) void k_stream_copy(const uint4* __restrict__ a,
-                                                        uint4* __restrict__ b, int64_t N) {
-    const int64_t stride = int64_t(gridDim.x) * kBlock;
-    int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    for (; k + 3 * stride < N; k += 4 * stride) {
-        const uint4 v0 = a[k], v1 = a[k + stride], v2 = a[k + 2 * stride], v3 = a[k + 3 * stride];
-        b[k] = v0;
-        b[k + stride] = v1;
-        b[k + 2 * stride] = v2;
-        b[k + 3 * stride] = v3;
+// Streaming copy: each workgroup copies one contiguous chunk, 16-byte
+// elements, four loads in flight per thread, non-temporal loads and stores
+// (the data is touched once, so it should not displace cached lines).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kCopyGrid = 16384;
+__global__ __launch_bounds__(kBlock) void k_stream_copy(const u32x4* __restrict__ a,
+                                                        u32x4* __restrict__ b, int64_t N,
+                                                        int64_t per) {
+    const int64_t s0 = int64_t(blockIdx.x) * per;
+    const int64_t e0 = s0 + per < N ? s0 + per : N;
+    for (int64_t k = s0 + threadIdx.x; k < e0; k += 4 * kBlock) {
+        u32x4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (k + u * kBlock < e0) v[u] = __builtin_nontemporal_load(a + k + u * kBlock);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (k + u * kBlock < e0) __builtin_nontemporal_store(v[u], b + k + u * kBlock);
     }
-    for (; k < N; k += stride) b[k] = a[k];
 }
 
 __global__ void k_copy_bytes(const unsigned char* __restrict__ a, unsigned char* __restrict__ b,
@@ -639,9 +645,11 @@ void launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s
     if (n16 > 0 && (reinterpret_cast<uintptr_t>(src) % 16 == 0) &&
         (reinterpret_cast<uintptr_t>(dst) % 16 == 0)) {
         int64_t g = (n16 + kBlock - 1) / kBlock;
-        if (g > 4096) g = 4096;
+        if (g > kCopyGrid) g = kCopyGrid;
+        const int64_t per = (n16 + g - 1) / g;
         hipLaunchKernelGGL(k_stream_copy, dim3(g), dim3(kBlock), 0, s,
-                           reinterpret_cast<const uint4*>(src), reinterpret_cast<uint4*>(dst), n16);
+                           reinterpret_cast<const u32x4*>(src), reinterpret_cast<u32x4*>(dst), n16,
+                           per);
         const int64_t rest = bytes - n16 * 16;
         if (rest > 0)
             hipLaunchKernelGGL(k_copy_bytes, dim3(1), dim3(64), 0, s,
