@@ -457,6 +457,9 @@ def main():
                         "algorithmic_bytes_per_launch": round(bytes_per_launch)}
             if rec:
                 roofline["traffic_gbs"] = round(rec["bytes_per_launch"] / avg_s / 1e9, 1)
+                roofline["traffic_counts"] = ("L2-miss bytes per launch (rocprofv3 FETCH_SIZE + "
+                                              "WRITE_SIZE, calibrated on the copy kernel); "
+                                              "Infinity Cache hits included")
         names = ["edge", "scatter", "matvec", "cg_update", "other"]
         kern = {names[c]: {"ms": round(float(cls_ms[c]), 3), "launches": int(cls_calls[c])}
                 for c in range(5)}
