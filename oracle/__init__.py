@@ -35,6 +35,7 @@ from .operators import (  # noqa: F401
     primal_objective,
     dual_objective,
     kkt_residuals,
+    distance_bound,
 )
 from .solvers import ssnal, admm, ama, solve_path  # noqa: F401
 from .labels import fusion_scale, cluster_labels, fusion_margins  # noqa: F401

@@ -198,3 +198,18 @@ def kkt_residuals(X, U, A, B, r, q):
     fd = dual_objective(Uf, A, B)
     eta = abs(fp - fd) / (1.0 + abs(fp) + abs(fd))
     return dict(R_D=RD, R_C=RC, R_U=RU, kkt=max(RD, RC, RU), eta=eta, f_p=fp, f_d=fd)
+
+
+def distance_bound(X, U, A, B, r, q):
+    """Upper bound on ||X - X*||_F for the unique solution X* of (CCM).
+
+    (CCM) is 1-strongly convex in X, so f_p(X) - f_p(X*) >= 1/2 ||X - X*||^2,
+    and weak duality gives f_p(X*) >= f_d(Pi_C U) for any U; hence
+    ||X - X*||^2 <= 2 (f_p(X) - f_d(Pi_C U)).  The gap is taken with a
+    rounding allowance of 1e-13 (1 + |f_p| + |f_d|) for the two sums.
+    Returns (bound, kkt_residuals(X, U, ...))."""
+    res = kkt_residuals(X, U, A, B, r, q)
+    fp, fd = res["f_p"], res["f_d"]
+    gap = max(fp - fd, 0.0) + 1e-13 * (1.0 + abs(fp) + abs(fd))
+    return float(np.sqrt(2.0 * gap)), res
+

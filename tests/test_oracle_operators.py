@@ -140,3 +140,33 @@ def test_weak_duality(q):
         X = rng.normal(size=(n, d))
         U = ops.project(rng.normal(size=(m, d)) * 3, r, q)
         assert ops.primal_objective(X, A, B, r, q) >= ops.dual_objective(U, A, B) - 1e-12
+
+
+def test_distance_bound_contains_the_solution():
+    # the bound from the duality gap is never below the true distance to X*,
+    # equals zero at the two-point closed form, and tightens as (X, U) do
+    from oracle import operators as ops
+    rng = np.random.default_rng(77)
+    A = rng.normal(size=(30, 3))
+    src, dst, w, *_ = oracle.knn_graph(A, 4, 0.5)
+    B = oracle.incidence(src, dst, 30)
+    for q in (1.0, 2.0, np.inf):
+        Xs, Us, _, _ = oracle.ssnal(A, src, dst, w, 0.3, q, 1e-12)
+        for eps in (1e-1, 1e-3, 1e-6):
+            Xp = Xs + eps * rng.normal(size=Xs.shape)
+            Up = Us + eps * rng.normal(size=Us.shape)
+            bound, res = ops.distance_bound(Xp, Up, A, B, 0.3 * w, q)
+            assert bound >= np.linalg.norm(Xp - Xs) * (1 - 1e-9), (q, eps)
+        b0, _ = ops.distance_bound(Xs, Us, A, B, 0.3 * w, q)
+        assert b0 <= 1e-5 * np.linalg.norm(Xs), q
+    # two points, q = 2: X* and U* in closed form give a zero gap
+    A2 = np.array([[0.0, 0.0], [3.0, 4.0]])
+    B2 = oracle.incidence(np.array([0]), np.array([1]), 2)
+    g, wl = 0.5, 1.0
+    delta = A2[0] - A2[1]
+    u = g * wl * delta / np.linalg.norm(delta)
+    X2 = A2 - (B2.T @ u[None, :])
+    b2, res2 = ops.distance_bound(X2, u[None, :], A2, B2, np.array([g * wl]), 2.0)
+    allowance = np.sqrt(2e-13 * (1 + abs(res2["f_p"]) + abs(res2["f_d"])))
+    assert b2 <= 1.01 * allowance and res2["kkt"] <= 1e-15
+    assert abs(res2["f_p"] - res2["f_d"]) <= 1e-13 * abs(res2["f_p"])
