@@ -12,7 +12,11 @@ hold at any size (GPU).
   two gammas an oracle SSNAL solve to 1e-10, started from the GPU's X at the
   previous gamma, is within 1e-5; labels equal the oracle's cluster rule on
   the GPU's X, and the centroid is kept up to the certified residual.
-* the adjoint at n = 2e4: one directional central difference of tight solves.
+* the adjoint at n = 2e4: at gamma = 0.5 (every point its own cluster) one
+  directional central difference of tight solves; at gamma = 8 (8 fused
+  clusters of 2500 points, the partition constant at every perturbed point)
+  the oracle's adjoint and central differences (h = 1e-6) in A, log w and
+  gamma.
 * batched instances at their full sizes (two per (q, d) group, KKT 5e-7):
   every instance converged; at two gammas the batched X is within 1e-5 of
   X*, bounded by its distance to a tight (1e-10) library solve of the
@@ -177,6 +181,66 @@ def test_vjp_mixture32_n20000_directional_difference():
     fd = (L(Xp) - L(Xm)) / (2 * h)
     an = float((host(gA) * D).sum())
     assert abs(an - fd) <= 1e-5 * max(1.0, abs(fd)), (an, fd)
+
+
+def test_vjp_mixture32_n20000_fused_clusters():
+    # gamma = 8 fuses each of the 8 blobs (2500 points) into one cluster: the
+    # adjoint runs in cluster space (the
+    # membership lists are far longer than a window).  The GPU VJP is checked
+    # against the oracle's adjoint and against central differences (h = 1e-6)
+    # of tight solves in three directions of A, one of log w and gamma.
+    torch, ccm = need_gpu()
+    A, _, T = synthdata.mixture32()
+    n = A.shape[0]
+    Ad = dev(A)
+    src, dst, w, _ = ccm.ccm_build_knn_graph(Ad, 10, 0.0)
+    hs, hd, hw = host(src), host(dst), host(w)
+    g = 8.0
+    out = ccm.ccm_solve_path(Ad, src, dst, w, [g], 2.0, 1e-12, want_U=True)
+    assert int(out["status"][0]) == 0
+    X, U, lab = out["X"][0], out["U"][0], out["labels"][0]
+    Xh, Uh = host(X), host(U)
+    S = oracle.fusion_scale(A)
+    B = oracle.incidence(hs, hd, n)
+    bound, res = ops.distance_bound(Xh, Uh, A, B, g * hw, 2.0)
+    assert res["kkt"] <= 1e-12 * 1.0001 and bound <= 1e-6 * np.linalg.norm(Xh)
+    olab, K = oracle.cluster_labels(Xh, hs, hd, n, S)
+    assert np.array_equal(host(lab), olab) and K == int(out["n_clusters"][0])
+    assert 1 < K <= n // 1000
+    # the oracle's own solve agrees; the partition is locally constant (the
+    # labels stay the same at every perturbed point below; dual slacks are
+    # not used here because U is not unique on the graph's cycles)
+    Xo, Uo, _, _ = oracle.ssnal(A, hs, hd, hw, g, 2.0, 1e-10, X0=Xh)
+    assert np.linalg.norm(Xh - Xo) <= 1e-6 * np.linalg.norm(Xo)
+    nd = np.linalg.norm(Xh[hs] - Xh[hd], axis=1)
+    inter = olab[hs] != olab[hd]
+    assert not inter.any() or nd[inter].min() > 1e-4 * (1 + S)
+    G = 2.0 * (Xh - T)
+    gA, glw, gg, iters = ccm.ccm_path_vjp(Ad, src, dst, w, g, X, lab, dev(G), tol=1e-13)
+    gA, glw = host(gA), host(glw)
+    rA, rlw, rg = oracle.path_vjp(A, hs, hd, hw, g, Xh, G, labels=olab)
+    assert np.linalg.norm(gA - rA) / np.linalg.norm(rA) <= 1e-6
+    assert np.linalg.norm(glw - rlw) <= 1e-6 * (1 + np.linalg.norm(rlw))
+    assert abs(gg - rg) <= 1e-6 * (1 + abs(rg))
+
+    def loss(Ax, wx, gx):
+        o = ccm.ccm_solve_path(Ax, src, dst, wx, [gx], 2.0, 1e-13)
+        assert int(o["status"][0]) == 0
+        assert torch.equal(o["labels"][0], lab)
+        return float(((host(o["X"][0]) - T) ** 2).sum())
+
+    h = 1e-6
+    rng = np.random.default_rng(903)
+    for _ in range(3):
+        V = rng.normal(size=A.shape)
+        fd = (loss(dev(A + h * V), w, g) - loss(dev(A - h * V), w, g)) / (2 * h)
+        an = float((gA * V).sum())
+        assert abs(fd - an) <= 1e-5 * (1 + abs(fd)), (fd, an)
+    v = rng.normal(size=hw.shape)
+    fd = (loss(Ad, dev(hw * np.exp(h * v)), g) - loss(Ad, dev(hw * np.exp(-h * v)), g)) / (2 * h)
+    assert abs(fd - float((glw * v).sum())) <= 1e-5 * (1 + abs(fd))
+    fd = (loss(Ad, w, g + h) - loss(Ad, w, g - h)) / (2 * h)
+    assert abs(fd - gg) <= 1e-5 * (1 + abs(fd))
 
 
 def test_batched_full_size_instances_certified():
