@@ -37,7 +37,7 @@ from .operators import (  # noqa: F401
     kkt_residuals,
     distance_bound,
 )
-from .solvers import ssnal, admm, ama, solve_path  # noqa: F401
+from .solvers import ssnal, admm, ama, hpr, solve_path  # noqa: F401
 from .labels import fusion_scale, cluster_labels, fusion_margins  # noqa: F401
 from .graph import knn_brute, knn_graph, knn_brute_u8, knn_graph_u8, canonicalize_edges  # noqa: F401
 from .adjoint import path_vjp  # noqa: F401

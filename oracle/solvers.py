@@ -78,6 +78,15 @@ ADMM_DEFAULTS = dict(
 
 AMA_DEFAULTS = dict(max_iter=100000, check_every=10)
 
+HPR_DEFAULTS = dict(
+    max_iter=20000,
+    sigma0=1.0,
+    check_every=10,
+    restart_sufficient=0.2,   # restart when the residual fell below 0.2 of the anchor's
+    restart_necessary=0.8,    # ... or below 0.8 of it and rose since the last check
+    restart_long=0.2,         # ... or the anchor is older than 0.2 of all iterations
+)
+
 
 def _diag_BtPB(Y, r, q, B_abs, d):
     """diag(B^T P B) as an n x d array: sum over incident edges of diag(P_l)."""
@@ -288,6 +297,103 @@ def admm(A, src, dst, w, gamma, q, tol=1e-6, X0=None, Z0=None, L0=None,
     return X, U, (Z, L, sig), info
 
 
+def hpr(A, src, dst, w, gamma, q, tol=1e-6, X0=None, Z0=None, L0=None,
+        sigma=None, opts=None, callback=None):
+    """Solve (CCM) at one gamma by the Halpern-Peaceman-Rachford method (the
+    conclusion's future-work algorithm; the paper states no steps).
+
+    The splitting is ADMM's, min f(X) + g(Z) s.t. BX = Z with
+    f = 1/2 ||X - A||^2 and g(Z) = sum_l r_l ||z_l||_q.  One Peaceman-Rachford
+    step T maps w = (Z, L) to (Zh, Lh):
+        X  = (I + sigma B^T B)^{-1} (A + B^T (sigma Z - L)),
+        H  = 2 B X - Z                        (reflection: relaxation 2),
+        Lh = Pi_C(sigma H + L),   Zh = H + (L - Lh) / sigma
+    (Zh is the prox of g / sigma at H + L / sigma by Moreau).  Halpern's
+    iteration anchors it at w0:  w <- w0 / (k + 2) + (k + 1) / (k + 2) T(w).
+    Every check_every iterations: stop when the relative KKT residual of
+    (X, Lh) is <= tol; restart the anchor (w0 <- w, k <- 0, sigma balanced
+    as in ADMM) when the fixed-point residual
+    R = (sigma ||Z - Zh||^2 + ||L - Lh||^2 / sigma)^(1/2) fell below 0.2 of
+    its value at the anchor, or below 0.8 of it while rising, or when the
+    anchor is older than 0.2 of the iterations so far.
+    Returns (X, U, (Z, L, sigma), info) with U = Lh (already in C)."""
+    o = dict(HPR_DEFAULTS)
+    if opts:
+        o.update(opts)
+    A = np.asarray(A, dtype=np.float64)
+    n, d = A.shape
+    m = len(src)
+    B = incidence(src, dst, n)
+    Bt = B.T.tocsr()
+    r = float(gamma) * np.asarray(w, dtype=np.float64)
+    sig = float(o["sigma0"] if sigma is None else sigma)
+    info = dict(iters=0, restarts=0)
+    if gamma == 0.0 or m == 0:
+        X = A.copy()
+        U = np.zeros((m, d))
+        info.update(kkt_residuals(X, U, A, B, r, q))
+        return X, U, (np.zeros((m, d)), np.zeros((m, d)), sig), info
+    X = A.copy() if X0 is None else np.array(X0, dtype=np.float64)
+    Z = (B @ X) if Z0 is None else np.array(Z0, dtype=np.float64)
+    L = np.zeros((m, d)) if L0 is None else np.array(L0, dtype=np.float64)
+    Lap = (Bt @ B).tocsc()
+    I = sp.identity(n, format="csc")
+    lu = spla.splu((I + sig * Lap).tocsc())
+    Za, La = Z.copy(), L.copy()      # anchor
+    k = 0
+    R_anchor = None
+    R_prev = None
+    res = None
+    U = None
+    for it in range(1, o["max_iter"] + 1):
+        info["iters"] = it
+        X = lu.solve(A + Bt @ (sig * Z - L))
+        BX = B @ X
+        H = 2.0 * BX - Z
+        Lh = project(sig * H + L, r, q)
+        Zh = H + (L - Lh) / sig
+        dz2 = float(((Z - Zh) ** 2).sum())
+        dl2 = float(((L - Lh) ** 2).sum())
+        rp2 = float(((BX - Zh) ** 2).sum())
+        U = Lh
+        a = 1.0 / (k + 2.0)
+        Z = a * Za + (1.0 - a) * Zh
+        L = a * La + (1.0 - a) * Lh
+        k += 1
+        if callback is not None:
+            callback(X)
+        if it % o["check_every"] == 0:
+            res = kkt_residuals(X, U, A, B, r, q)
+            if res["kkt"] <= tol:
+                break
+            R = np.sqrt(sig * dz2 + dl2 / sig)
+            if R_anchor is None:
+                R_anchor = R
+            elif (R <= o["restart_sufficient"] * R_anchor
+                  or (R <= o["restart_necessary"] * R_anchor and R_prev is not None
+                      and R > R_prev)
+                  or k >= o["restart_long"] * it):
+                info["restarts"] += 1
+                Za, La = Z.copy(), L.copy()
+                k = 0
+                rp = np.sqrt(rp2)
+                rd = sig * np.sqrt(dz2)
+                if rp > 10.0 * rd:
+                    sig *= 2.0
+                    lu = spla.splu((I + sig * Lap).tocsc())
+                elif rd > 10.0 * rp:
+                    sig *= 0.5
+                    lu = spla.splu((I + sig * Lap).tocsc())
+                R_anchor = np.sqrt(sig * dz2 + dl2 / sig)
+                R_prev = None
+                continue
+            R_prev = R
+    if res is None or info["iters"] % o["check_every"] != 0:
+        res = kkt_residuals(X, U, A, B, r, q)
+    info.update(res)
+    return X, U, (Z, L, sig), info
+
+
 def ama(A, src, dst, w, gamma, q, tol=1e-6, U0=None, opts=None):
     """Solve (CCM) at one gamma by fast AMA (accelerated dual projected
     gradient).  Returns (X, U, info)."""
@@ -358,6 +464,9 @@ def solve_path(A, src, dst, w, gammas, q, tol=1e-6, method="ssnal", opts=None):
                                            sigma=sig, opts=opts)
         elif method == "ama":
             X, U, info = ama(A, src, dst, w, g, q, tol, U0=U, opts=opts)
+        elif method == "hpr":
+            X, U, (Z, L, sig), info = hpr(A, src, dst, w, g, q, tol, X0=X, Z0=Z, L0=L,
+                                          sigma=sig, opts=opts)
         else:
             raise ValueError(method)
         out["seconds"].append(time.perf_counter() - t0)

@@ -11,7 +11,7 @@ from oracle import operators as ops
 from oracle.brute import dual_slsqp, primal_value, proj_l1_bisection
 
 QS = [1.0, 2.0, np.inf]
-SOLVERS = ["ssnal", "admm", "ama"]
+SOLVERS = ["ssnal", "admm", "ama", "hpr"]
 
 
 def solve(method, A, src, dst, w, g, q, tol=1e-10):
@@ -19,6 +19,8 @@ def solve(method, A, src, dst, w, g, q, tol=1e-10):
         X, U, _, info = oracle.ssnal(A, src, dst, w, g, q, tol)
     elif method == "admm":
         X, U, _, info = oracle.admm(A, src, dst, w, g, q, tol)
+    elif method == "hpr":
+        X, U, _, info = oracle.hpr(A, src, dst, w, g, q, tol)
     else:
         X, U, info = oracle.ama(A, src, dst, w, g, q, tol)
     return X, U, info
@@ -100,6 +102,11 @@ def test_centroid_preserved(q):
         return np.abs(got - target).max() / (1 + np.abs(target).max())
 
     oracle.admm(A, src, dst, w, 0.2, q, 1e-8, callback=lambda X: seen.append(dev(X)))
+    assert len(seen) > 0
+    assert max(seen) <= 1e-12
+    # HPR solves the same X system exactly at every iterate
+    seen.clear()
+    oracle.hpr(A, src, dst, w, 0.2, q, 1e-8, callback=lambda X: seen.append(dev(X)))
     assert len(seen) > 0
     assert max(seen) <= 1e-12
     X, U, _, info = oracle.ssnal(A, src, dst, w, 0.2, q, 1e-10)
@@ -249,7 +256,7 @@ def test_solvers_agree_on_path(q):
     src, dst, w, *_ = oracle.knn_graph(A, 6, 0.5)
     gs = synthdata.gamma_grid(-2, 0.5, 5)
     ref = oracle.solve_path(A, src, dst, w, gs, q, 1e-9, method="ssnal")
-    for method in ("admm", "ama"):
+    for method in ("admm", "ama", "hpr"):
         out = oracle.solve_path(A, src, dst, w, gs, q, 1e-9, method=method)
         for t in range(len(gs)):
             rel = np.linalg.norm(out["X"][t] - ref["X"][t]) / np.linalg.norm(ref["X"][t])
