@@ -331,14 +331,14 @@ def q_leg(ccm, torch, A, graph, wl, q):
 
 
 def small_workload_leg(ccm, torch, name, steps=3):
-    """A smaller configuration, k-NN + path per step, by SSNAL and by ADMM."""
+    """A smaller configuration, k-NN + path per step, by SSNAL, ADMM and HPR."""
     wl = WORKLOADS[name]
     A_np, _ = make_points(wl)
     A = torch.from_numpy(A_np).cuda()
     lo, hi, cnt = wl["gammas"]
     gammas = np.logspace(lo, hi, int(cnt))
     rec = {"desc": wl["desc"], "n": int(A_np.shape[0]), "d": int(A_np.shape[1])}
-    for method, code in (("ssnal", 0), ("admm", 1)):
+    for method, code in (("ssnal", 0), ("admm", 1), ("hpr", 3)):
         o = ccm.ccm_default_options(method=code)
 
         def one():
@@ -367,7 +367,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--no-q-legs", action="store_true", help="skip the q = 1 and q = inf legs")
     ap.add_argument("--no-workloads", action="store_true",
-                    help="skip the smaller-configuration legs (SSNAL and ADMM)")
+                    help="skip the smaller-configuration legs (SSNAL, ADMM and HPR)")
     ap.add_argument("--batched-count", type=int, default=512)
     ap.add_argument("--batched-budget", type=float, default=90.0,
                     help="wall-clock budget (s) of each (q, d) group of the batched leg")

@@ -61,7 +61,11 @@ enum {
                                tolerance (outputs hold its last iterate) */
 };
 
-enum { CCM_SSNAL = 0, CCM_ADMM = 1, CCM_AMA = 2 };            /* solver */
+/* solver: SSNAL and ADMM (Section 1, Table 3), fast AMA (Table 3), and the
+ * Halpern-Peaceman-Rachford method named as future work in the conclusion
+ * (CCM_HPR: ADMM's splitting with the Peaceman-Rachford relaxation 2 inside
+ * Halpern's anchored iteration, anchor restarts on the fixed-point residual) */
+enum { CCM_SSNAL = 0, CCM_ADMM = 1, CCM_AMA = 2, CCM_HPR = 3 };
 enum { CCM_CONVERGED = 0, CCM_MAX_ITER = 1, CCM_TIMEOUT = 2,
        CCM_NUMERICAL = 3 };                                   /* per-gamma status */
 
@@ -80,12 +84,12 @@ ccm_status ccm_release_workspace(void);
  * the unique solution X*.
  */
 typedef struct {
-    int32_t method;        /* CCM_SSNAL (default), CCM_ADMM or CCM_AMA */
+    int32_t method;        /* CCM_SSNAL (default), CCM_ADMM, CCM_AMA or CCM_HPR */
     int32_t max_outer;     /* SSNAL outer (augmented Lagrangian) iterations per gamma. 300 */
     int32_t max_newton;    /* SSNAL Newton steps per outer iteration.  60 */
     int32_t cg_max_iter;   /* CG iterations per linear solve.  500 */
-    int32_t max_iter;      /* ADMM / AMA iterations per gamma.  20000 */
-    int32_t check_every;   /* ADMM / AMA: KKT test every this many iterations.  10 */
+    int32_t max_iter;      /* ADMM / AMA / HPR iterations per gamma.  20000 */
+    int32_t check_every;   /* ADMM / AMA / HPR: KKT test every this many iterations.  10 */
     int32_t cg_chunk;      /* CG iterations launched between host checks.  8 */
     int32_t profile;       /* 1: time every kernel class with HIP events (ccm_stats.kern_*);
                               2: time only the Newton/CG matvec class (less host work);

@@ -311,11 +311,13 @@ def hpr(A, src, dst, w, gamma, q, tol=1e-6, X0=None, Z0=None, L0=None,
     (Zh is the prox of g / sigma at H + L / sigma by Moreau).  Halpern's
     iteration anchors it at w0:  w <- w0 / (k + 2) + (k + 1) / (k + 2) T(w).
     Every check_every iterations: stop when the relative KKT residual of
-    (X, Lh) is <= tol; restart the anchor (w0 <- w, k <- 0, sigma balanced
-    as in ADMM) when the fixed-point residual
-    R = (sigma ||Z - Zh||^2 + ||L - Lh||^2 / sigma)^(1/2) fell below 0.2 of
-    its value at the anchor, or below 0.8 of it while rising, or when the
-    anchor is older than 0.2 of the iterations so far.
+    (X, Lh) is <= tol; restart the anchor (w0 <- w, k <- 0) when the
+    fixed-point residual R = (sigma ||Z - Zh||^2 + ||L - Lh||^2 / sigma)^(1/2)
+    fell below 0.2 of its value at the anchor, or below 0.8 of it while
+    rising, or when the anchor is older than 0.2 of the iterations so far.
+    At a restart sigma becomes ||L - L0|| / ||Z - Z0|| (the movement since
+    the anchor; it balances the two terms of the weighted norm), kept within
+    a factor 10 of the old sigma.
     Returns (X, U, (Z, L, sigma), info) with U = Lh (already in C)."""
     o = dict(HPR_DEFAULTS)
     if opts:
@@ -354,7 +356,6 @@ def hpr(A, src, dst, w, gamma, q, tol=1e-6, X0=None, Z0=None, L0=None,
         Zh = H + (L - Lh) / sig
         dz2 = float(((Z - Zh) ** 2).sum())
         dl2 = float(((L - Lh) ** 2).sum())
-        rp2 = float(((BX - Zh) ** 2).sum())
         U = Lh
         a = 1.0 / (k + 2.0)
         Z = a * Za + (1.0 - a) * Zh
@@ -374,16 +375,13 @@ def hpr(A, src, dst, w, gamma, q, tol=1e-6, X0=None, Z0=None, L0=None,
                       and R > R_prev)
                   or k >= o["restart_long"] * it):
                 info["restarts"] += 1
+                mz = np.linalg.norm(Z - Za)
+                ml = np.linalg.norm(L - La)
+                if mz > 0.0 and ml > 0.0:
+                    sig = min(max(ml / mz, 0.1 * sig), 10.0 * sig)
+                    lu = spla.splu((I + sig * Lap).tocsc())
                 Za, La = Z.copy(), L.copy()
                 k = 0
-                rp = np.sqrt(rp2)
-                rd = sig * np.sqrt(dz2)
-                if rp > 10.0 * rd:
-                    sig *= 2.0
-                    lu = spla.splu((I + sig * Lap).tocsc())
-                elif rd > 10.0 * rp:
-                    sig *= 0.5
-                    lu = spla.splu((I + sig * Lap).tocsc())
                 R_anchor = np.sqrt(sig * dz2 + dl2 / sig)
                 R_prev = None
                 continue

@@ -15,7 +15,7 @@ import os
 import numpy as np
 
 __all__ = [
-    "CCM_SSNAL", "CCM_ADMM", "CCM_AMA",
+    "CCM_SSNAL", "CCM_ADMM", "CCM_AMA", "CCM_HPR",
     "CCM_CONVERGED", "CCM_MAX_ITER", "CCM_TIMEOUT", "CCM_NUMERICAL",
     "CcmError", "CcmOptions", "CcmStats", "lib", "library_path",
     "ccm_version", "ccm_default_options", "ccm_build_knn_graph", "ccm_solve_path",
@@ -28,7 +28,7 @@ __all__ = [
 
 CCM_E_NOT_CONVERGED = 6
 
-CCM_SSNAL, CCM_ADMM, CCM_AMA = 0, 1, 2
+CCM_SSNAL, CCM_ADMM, CCM_AMA, CCM_HPR = 0, 1, 2, 3
 CCM_CONVERGED, CCM_MAX_ITER, CCM_TIMEOUT, CCM_NUMERICAL = 0, 1, 2, 3
 CCM_NK = 5
 

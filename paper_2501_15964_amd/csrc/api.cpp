@@ -333,7 +333,8 @@ ccm_status ccm_solve_path(const double* A, int64_t n, int64_t d, const int32_t* 
     if (!q_kind(q, qk)) return fail(CCM_E_UNSUPPORTED, "q must be 1, 2 or inf");
     if (!(tol > 0) || !std::isfinite(tol)) return fail(CCM_E_INVALID, "tol must be > 0");
     ccm_options o = opts ? *opts : defaults();
-    if (o.method != CCM_SSNAL && o.method != CCM_ADMM && o.method != CCM_AMA)
+    if (o.method != CCM_SSNAL && o.method != CCM_ADMM && o.method != CCM_AMA &&
+        o.method != CCM_HPR)
         return fail(CCM_E_INVALID, "unknown method");
     if (o.max_outer < 1 || o.max_newton < 1 || o.cg_max_iter < 1 || o.max_iter < 1)
         return fail(CCM_E_INVALID, "iteration limits must be >= 1");

@@ -222,6 +222,69 @@ __global__ __launch_bounds__(kBlock) void k_edge_admm(int64_t m, int d, const in
     block_reduce_store<kEdgeAdmmNV>(acc, partials + blockIdx.x * kEdgeAdmmNV);
 }
 
+// One Halpern-Peaceman-Rachford edge step (see launch_edge_hpr).
+template <int LPR, int NPER, int Q>
+__global__ __launch_bounds__(kBlock) void k_edge_hpr(int64_t m, int d, const int* __restrict__ src,
+                                                     const int* __restrict__ dst,
+                                                     const double* __restrict__ w, double gamma,
+                                                     double sigma, double a,
+                                                     const double* __restrict__ X,
+                                                     double* __restrict__ Z,
+                                                     double* __restrict__ L,
+                                                     const double* __restrict__ Za,
+                                                     const double* __restrict__ La,
+                                                     double* __restrict__ Qo,
+                                                     double* __restrict__ Uh,
+                                                     double* __restrict__ partials) {
+    const int lane = threadIdx.x & 63;
+    const int gl = lane % LPR;
+    constexpr int GPB = kBlock / LPR;
+    double acc[kEdgeHprNV] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t l = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; l < m;
+         l += int64_t(gridDim.x) * GPB) {
+        const int64_t i = src[l], j = dst[l];
+        const double r = gamma * w[l];
+        double bx[NPER], lam[NPER], zo[NPER], y[NPER];
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            if (k < d) {
+                bx[t] = X[i * d + k] - X[j * d + k];
+                lam[t] = L[l * d + k];
+                zo[t] = Z[l * d + k];
+            } else {
+                bx[t] = lam[t] = zo[t] = 0.0;
+            }
+            // reflection H = 2 BX - Z, then the point sigma H + L to project
+            y[t] = sigma * (2.0 * bx[t] - zo[t]) + lam[t];
+        }
+        RowProj<LPR, NPER, Q> o;
+        project_row<LPR, NPER, Q, false>(y, gl, lane, d, r, o);
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            if (k < d) {
+                const double h = 2.0 * bx[t] - zo[t];
+                const double lh = o.pi[t];
+                const double zh = h + (lam[t] - lh) / sigma;
+                const double zn = a * Za[l * d + k] + (1.0 - a) * zh;
+                const double ln = a * La[l * d + k] + (1.0 - a) * lh;
+                Z[l * d + k] = zn;
+                L[l * d + k] = ln;
+                Qo[l * d + k] = sigma * zn - ln;
+                if (Uh) Uh[l * d + k] = lh;
+                const double dz = zo[t] - zh, dl = lam[t] - lh;
+                const double mz = zn - Za[l * d + k], ml = ln - La[l * d + k];
+                acc[0] += dz * dz;
+                acc[1] += dl * dl;
+                acc[2] += mz * mz;
+                acc[3] += ml * ml;
+            }
+        }
+    }
+    block_reduce_store<kEdgeHprNV>(acc, partials + blockIdx.x * kEdgeHprNV);
+}
+
 template <int LPR, int NPER, int Q>
 __global__ __launch_bounds__(kBlock) void k_edge_ama(int64_t m, int d, const int* __restrict__ src,
                                                      const int* __restrict__ dst,
@@ -388,6 +451,23 @@ int launch_edge_admm(const DevGraph& g, int d, int qk, double gamma, double sigm
             constexpr int q = decltype(Qc)::value;
             hipLaunchKernelGGL((k_edge_admm<lpr, nper, q>), dim3(grid), dim3(kBlock), 0, s, g.m,
                                d, g.src, g.dst, g.w, gamma, sigma, tau, X, Z, L_, Q, Uf, partials);
+        });
+    });
+    return grid;
+}
+
+int launch_edge_hpr(const DevGraph& g, int d, int qk, double gamma, double sigma, double a,
+                    const double* X, double* Z, double* L_, const double* Za, const double* La,
+                    double* Q, double* Uh, double* partials, hipStream_t s) {
+    int grid = 1;
+    dispatch_row(d, [&](auto L, auto N) {
+        constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
+        grid = row_grid(g.m, lpr);
+        dispatch_q(qk, [&](auto Qc) {
+            constexpr int q = decltype(Qc)::value;
+            hipLaunchKernelGGL((k_edge_hpr<lpr, nper, q>), dim3(grid), dim3(kBlock), 0, s, g.m,
+                               d, g.src, g.dst, g.w, gamma, sigma, a, X, Z, L_, Za, La, Q, Uh,
+                               partials);
         });
     });
     return grid;

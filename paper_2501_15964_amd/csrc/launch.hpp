@@ -157,6 +157,16 @@ int launch_edge_admm(const DevGraph& g, int d, int qk, double gamma, double sigm
                      const double* X, double* Z, double* L, double* Q, double* Uf,
                      double* partials, hipStream_t s);
 
+// Halpern-Peaceman-Rachford edge step on the state (Z, L) with anchor
+// (Za, La) and Halpern weight a: H = 2 BX - Z, Lh = Pi_C(sigma H + L),
+// Zh = H + (L - Lh) / sigma; Z <- a Za + (1 - a) Zh, L <- a La + (1 - a) Lh,
+// Q <- sigma Z - L, optional Uh <- Lh.  partials (4): ||Z - Zh||^2,
+// ||L - Lh||^2 (Z, L before the step), ||Z - Za||^2, ||L - La||^2 (after).
+constexpr int kEdgeHprNV = 4;
+int launch_edge_hpr(const DevGraph& g, int d, int qk, double gamma, double sigma, double a,
+                    const double* X, double* Z, double* L, const double* Za, const double* La,
+                    double* Q, double* Uh, double* partials, hipStream_t s);
+
 // Fast AMA edge step on the dual: Unew = Pi_C(V + nu B X); then with momentum
 // coefficient beta: Vnew = Unew + beta (Unew - U); U <- Unew.  partials (2):
 // <V - Unew, Unew - U> (restart test), ||Unew - U||^2.

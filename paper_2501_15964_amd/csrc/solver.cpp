@@ -183,7 +183,7 @@ struct Solver::Impl {
     DevMem bX, bXt, bG, bGt, bDinv, bDinvt, bTmp, bTmp2;
     DevMem cgx, cgr, cgu, cgw, cgp, cgs;
     // edge buffers
-    DevMem bU, bPi, bPit, bZ, bL, bQ, bZold;
+    DevMem bU, bPi, bPit, bZ, bL, bQ, bZold, bLa;
     DevMem ip0, ip1, lb0, lb1;  // Jacobian payload (current, trial)
     int cg_pred[2] = {8, 8};    // predicted CG iterations (Newton, Laplacian systems)
     DevMem fused, parent, rank, ltemp;
@@ -250,11 +250,12 @@ struct Solver::Impl {
                 HIPCHK(lb0.alloc(lw * 4, s));
                 HIPCHK(lb1.alloc(lw * 4, s));
             }
-        } else if (o.method == CCM_ADMM) {
+        } else if (o.method == CCM_ADMM || o.method == CCM_HPR) {
             HIPCHK(bZ.alloc(eb, s));
             HIPCHK(bL.alloc(eb, s));
             HIPCHK(bQ.alloc(eb, s));
-            HIPCHK(bZold.alloc(eb, s));
+            HIPCHK(bZold.alloc(eb, s));  // HPR: the anchor's Z
+            if (o.method == CCM_HPR) HIPCHK(bLa.alloc(eb, s));
         } else {
             HIPCHK(bZ.alloc(eb, s));  // momentum point V
         }
@@ -910,6 +911,106 @@ struct Solver::Impl {
         if (status != CCM_CONVERGED) CHK(kkt_last_admm(gamma, res));
         return CCM_OK;
     }
+    // ---- Halpern-Peaceman-Rachford at one gamma --------------------------------
+    // The Peaceman-Rachford step of ADMM's splitting (exact X solve by CG as
+    // in ADMM, reflection H = 2 BX - Z, multiplier Pi_C(sigma H + L)) inside
+    // Halpern's iteration anchored at (Za, La); every check_every iterations
+    // the KKT test at (X, Lh) and the anchor restart test on the fixed-point
+    // residual R = (sigma ||Z - Zh||^2 + ||L - Lh||^2 / sigma)^(1/2):
+    // restart when R fell below 0.2 of its anchor value, below 0.8 of it
+    // while rising, or when the anchor is older than 0.2 of the iterations;
+    // at a restart sigma becomes ||L - La|| / ||Z - Za|| within a factor 10
+    // of the old value.  The state (Z, L, sigma) is carried to the next gamma.
+    ccm_status hpr(double gamma, int& status, ccm_stats& st, double (&res)[7]) {
+        const int ce = std::max(1, o.check_every);
+        double* Z = bZ.as<double>();
+        double* L = bL.as<double>();
+        double* Q = bQ.as<double>();
+        double* Za = bZold.as<double>();
+        double* La = bLa.as<double>();
+        double* R = bTmp.as<double>();
+        double* T = bTmp2.as<double>();
+        status = CCM_MAX_ITER;
+        if (!admm_state) {
+            launch_gather(g, d, X, Z, s);
+            launch_fill(L, M, 0.0, s);
+            admm_state = true;
+        }
+        launch_axpby(sigma, Z, -1.0, L, Q, M, s);
+        launch_lap_dinv(g, d, 1.0, sigma, Dinv, s);
+        launch_copy(Z, Za, M, s);
+        launch_copy(L, La, M, s);
+        const double thr_abs = 0.01 * tol * (1.0 + nA);
+        int k = 0;
+        double R_anchor = -1.0, R_prev = -1.0;
+        for (int it = 1; it <= o.max_iter; ++it) {
+            st.outer++;
+            {
+                Timed t(prof, CCM_K_SCATTER);
+                launch_scatter(g, d, qk, 0.0, nullptr, 1.0, A, 1.0, Q, R, false, Payload{}, gamma,
+                               sigma, nullptr, ps.as<double>(), s);
+            }
+            {
+                Timed t(prof, CCM_K_MATVEC, lap_bytes());
+                launch_matvec(g, d, qk, 1, X, nullptr, Payload{}, gamma, sigma, 1.0, nullptr, T,
+                              pm2.as<double>(), CgSkip{}, s);
+            }
+            launch_sub(R, T, R, N, s);
+            int iters = 0;
+            CHK(cg_solve(1, R, false, Dinv, thr_abs * thr_abs, gamma, nullptr, Payload{}, iters));
+            st.cg += iters;
+            launch_axpy(X, 1.0, cg.x, N, s);
+            const bool check = (it % ce) == 0;
+            {
+                Timed t(prof, CCM_K_EDGE);
+                const double a = 1.0 / (double(k) + 2.0);
+                const int gp = launch_edge_hpr(g, d, qk, gamma, sigma, a, X, Z, L, Za, La, Q,
+                                               check ? U : nullptr, pe.as<double>(), s);
+                defer_finalize(pe.as<double>(), gp, kEdgeHprNV, slot(kM), s);
+            }
+            ++k;
+            if (!check) continue;
+            CHK(kkt_of(U, gamma, G, res));
+            if (!std::isfinite(res[6])) {
+                status = CCM_NUMERICAL;
+                break;
+            }
+            if (res[6] <= tol) {
+                status = CCM_CONVERGED;
+                break;
+            }
+            if (out_of_time()) {
+                status = CCM_TIMEOUT;
+                break;
+            }
+            const double dz2 = hs[kM + 0], dl2 = hs[kM + 1];
+            const double mz = std::sqrt(hs[kM + 2]), ml = std::sqrt(hs[kM + 3]);
+            const double Rk = std::sqrt(sigma * dz2 + dl2 / sigma);
+            if (R_anchor < 0.0) {
+                R_anchor = Rk;
+            } else if (Rk <= 0.2 * R_anchor || (Rk <= 0.8 * R_anchor && R_prev >= 0.0 &&
+                                                Rk > R_prev) ||
+                       double(k) >= 0.2 * double(it)) {
+                launch_copy(Z, Za, M, s);
+                launch_copy(L, La, M, s);
+                k = 0;
+                double ns = sigma;
+                if (mz > 0.0 && ml > 0.0) ns = std::min(std::max(ml / mz, 0.1 * sigma), 10.0 * sigma);
+                if (ns != sigma) {
+                    sigma = ns;
+                    launch_axpby(sigma, Z, -1.0, L, Q, M, s);
+                    launch_lap_dinv(g, d, 1.0, sigma, Dinv, s);
+                }
+                R_anchor = std::sqrt(sigma * dz2 + dl2 / sigma);
+                R_prev = -1.0;
+                continue;
+            }
+            R_prev = Rk;
+        }
+        if (status != CCM_CONVERGED) CHK(kkt_last_admm(gamma, res));
+        return CCM_OK;
+    }
+
     ccm_status kkt_last_admm(double gamma, double (&res)[7]) {
         // U <- Pi_C(L) through the KKT edge pass with U = L (writes Pi_C(L))
         {
@@ -1088,6 +1189,8 @@ ccm_status Solver::run_path(const double* gammas, int T, const double* Xw, const
             CHK(I.ssnal(gamma, stat, st, res));
         } else if (I.o.method == CCM_ADMM) {
             CHK(I.admm(gamma, stat, st, res));
+        } else if (I.o.method == CCM_HPR) {
+            CHK(I.hpr(gamma, stat, st, res));
         } else {
             CHK(I.ama(gamma, stat, st, res));
         }

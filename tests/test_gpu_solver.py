@@ -10,7 +10,7 @@ from gpu_util import need_gpu, dev, host, graph_dev, rel
 pytestmark = pytest.mark.gpu
 
 QS = [1.0, 2.0, np.inf]
-METHODS = {"ssnal": 0, "admm": 1, "ama": 2}
+METHODS = {"ssnal": 0, "admm": 1, "ama": 2, "hpr": 3}
 
 
 def _opts(ccm, method, **kw):
@@ -46,7 +46,7 @@ def _compare_path(A, src, dst, w, gammas, q, method, tol_gpu, tol_oracle=1e-10,
     return out, ref
 
 
-@pytest.mark.parametrize("method", ["ssnal", "admm"])
+@pytest.mark.parametrize("method", ["ssnal", "admm", "hpr"])
 def test_blobs2d_path(method):
     A, _ = synthdata.blobs2d()
     src, dst, w, *_ = oracle.knn_graph(A, 10, 0.5)
@@ -60,6 +60,14 @@ def test_small_path_all_q(q):
     src, dst, w, *_ = oracle.knn_graph(A, 6, None)
     gammas = synthdata.gamma_grid(-2, 1, 6)
     _compare_path(A, src, dst, w, gammas, q, "ssnal", 1e-8, x_tol=1e-6)
+
+
+@pytest.mark.parametrize("q", QS)
+def test_hpr_small_all_q(q):
+    A, _ = synthdata.mixture64(n_per=30, d=5, n_blobs=4, seed=1401)
+    src, dst, w, *_ = oracle.knn_graph(A, 6, None)
+    gammas = synthdata.gamma_grid(-2, 1, 5)
+    _compare_path(A, src, dst, w, gammas, q, "hpr", 1e-8, x_tol=1e-6)
 
 
 @pytest.mark.parametrize("q", QS)
