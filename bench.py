@@ -65,6 +65,10 @@ WORKLOADS = {
 
 METRIC = "path wall-time @KKT 1e-6 + edge-op HBM GB/s %peak; plain vs batched/adjoint"
 
+# CG iterations replayed from captured HIP graphs in the legs that run
+# without kernel timing (ccm_options.graphs); set from --graphs
+GRAPHS = 0
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -241,7 +245,7 @@ def batched_leg(ccm, torch, count, budget_s):
         dev.append(dict(A=A, src=src, dst=dst, w=w, q=it["q"]))
     torch.cuda.synchronize()
     g = np.logspace(-3, 1, 10)
-    o = ccm.ccm_default_options(time_budget_s=budget_s)
+    o = ccm.ccm_default_options(time_budget_s=budget_s, graphs=GRAPHS)
     t0 = time.perf_counter()
     res = ccm.ccm_solve_path_batched(dev, g, 1e-6, opts=o)
     torch.cuda.synchronize()
@@ -339,7 +343,7 @@ def small_workload_leg(ccm, torch, name, steps=3):
     gammas = np.logspace(lo, hi, int(cnt))
     rec = {"desc": wl["desc"], "n": int(A_np.shape[0]), "d": int(A_np.shape[1])}
     for method, code in (("ssnal", 0), ("admm", 1), ("hpr", 3)):
-        o = ccm.ccm_default_options(method=code)
+        o = ccm.ccm_default_options(method=code, graphs=GRAPHS)
 
         def one():
             t0 = time.perf_counter()
@@ -373,6 +377,9 @@ def main():
                     help="wall-clock budget (s) of each (q, d) group of the batched leg")
     ap.add_argument("--locality", type=int, default=-1, choices=(-1, 0, 1),
                     help="vertex processing order of the library (-1: its default)")
+    ap.add_argument("--graphs", type=int, default=0, choices=(0, 1),
+                    help="replay CG iterations from captured HIP graphs where kernels are "
+                         "not timed")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without HIP events around the matvec launches (roofline then "
                          "omitted)")
@@ -385,6 +392,8 @@ def main():
     import torch
     import paper_2501_15964_amd as ccm
 
+    global GRAPHS
+    GRAPHS = args.graphs
     wl = WORKLOADS[args.workload]
     log(f"generating {args.workload} ...")
     A_np, K_np = make_points(wl)

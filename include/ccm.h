@@ -106,6 +106,10 @@ typedef struct {
                               the caches hold them); 0: the input order; -1
                               (default): 1 when n d >= 2^22, else 0.  Changes the
                               summation order only, never the data layout */
+    int32_t graphs;        /* 1: CG iterations are replayed two at a time from HIP graphs
+                              captured once per call (same kernels, bit-identical
+                              results, fewer launches); 0 (default): plain launches.
+                              Not used while profile != 0 */
 } ccm_options;
 
 ccm_options ccm_default_options(void);

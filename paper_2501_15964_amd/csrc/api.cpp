@@ -80,6 +80,7 @@ ccm_options defaults() {
     o.tau = 1.618;
     o.time_budget_s = 0.0;
     o.locality = -1;
+    o.graphs = 0;
     return o;
 }
 

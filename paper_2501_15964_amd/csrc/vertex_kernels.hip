@@ -691,6 +691,7 @@ struct MatvecOut {
     double sigma, c0;
     const double* dscale;
     double* out;
+    const double* sigma_dev;  // if set, sigma is read here at run time
 };
 
 template <int LPR, int NPER>
@@ -713,8 +714,9 @@ __device__ __forceinline__ void matvec_finish(int64_t v, int d, int gl, const Ma
 __device__ __forceinline__ bool cg_skip(const CgSkip& skip) {
     const int dn = skip.done ? *skip.done : 0;
     if (skip.rr_partials) {
+        const double thr = skip.thr_dev ? *skip.thr_dev : skip.thr;
         const double rr = block_sum_partials(skip.rr_partials, skip.nparts, 2, 1);
-        if (rr <= skip.thr) return true;
+        if (rr <= thr) return true;
     }
     return dn != 0;
 }
@@ -786,6 +788,7 @@ __global__ __launch_bounds__(kBlock, matvec_min_waves<NPER>()) void k_matvec_win
                                                        double* __restrict__ partials,
                                                        CgSkip skip) {
     if (cg_skip(skip)) return;
+    if (mo.sigma_dev) mo.sigma = *mo.sigma_dev;
     constexpr int U = Unroll<NPER>::U;
     constexpr bool PAY = MODE != 1;
     constexpr int QP = MODE == 2 ? kQ2 : Q;
@@ -994,10 +997,11 @@ int launch_edge_grad(const DevGraph& g, int d, int qk, double gamma, double sigm
 
 int launch_matvec(const DevGraph& g, int d, int qk, int mode, const double* V, const double* Pi,
                   Payload pl, double gamma, double sigma, double c0, const double* dscale,
-                  double* out, double* partials, CgSkip skip, hipStream_t s) {
+                  double* out, double* partials, CgSkip skip, hipStream_t s,
+                  const double* sigma_dev) {
     (void)gamma;  // the Jacobian payload already holds 1 / (gamma w)
     int total = 0;
-    MatvecOut mo{sigma, c0, dscale, out};
+    MatvecOut mo{sigma, c0, dscale, out, sigma_dev};
     dispatch_row(d, [&](auto L, auto N) {
         constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
         const int g1 = window_grid<lpr>(g);
