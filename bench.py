@@ -439,6 +439,8 @@ def main():
     status = [int(s) for s in out["status"]]
     knn_ms = 1000.0 * float(np.mean([r[1] for r in results]))
     path_ms = 1000.0 * float(np.mean([r[2] for r in results]))
+    setup_ms = 1000.0 * float(np.mean([r[2] - sum(st["seconds"] for st in r[0]["stats"])
+                                       for r in results]))
 
     roofline = None
     kern = None
@@ -495,7 +497,11 @@ def main():
         "config": {"workload": args.workload, "desc": wl["desc"], "n": n, "d": d,
                    "k": wl["k"], "m": m, "phi": phi, "q": wl["q"], "n_gamma": int(cnt),
                    "tol": wl["tol"], "method": "ssnal", "parallelism": "single-gpu"},
-        "phases_ms": {"knn_graph": round(knn_ms, 2), "path": round(path_ms, 2)},
+        "phases_ms": {"knn_graph": round(knn_ms, 2), "path": round(path_ms, 2),
+                      # inside the path call, before the first gamma: argument
+                      # checks, canonical edges, incidence lists, locality
+                      # order, windows, work space
+                      "path_setup": round(setup_ms, 2)},
         "max_kkt": kkt_max,
         "status": status,
         "n_clusters": [int(c) for c in out["n_clusters"]],

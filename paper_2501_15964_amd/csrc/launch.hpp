@@ -240,7 +240,8 @@ struct CgBufs {
     int nparts;                     // partial count of the update kernel
     int nparts_mv;                  // partial count of the matvec kernel
 };
-// r = b (or -b when neg), u = Dinv r, x = p = s = 0; partials ru[0], rr[0].
+// r = b (or -b when neg), u = Dinv r, x = 0 (iteration 0 writes p and s without reading
+// them); partials ru[0], rr[0].
 void launch_cg_init(int64_t N, const double* b, bool neg, const double* Dinv, CgBufs& cg,
                     hipStream_t s);
 // iteration j of the Chronopoulos-Gear PCG update (see vector_kernels.hip).

@@ -20,9 +20,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t N, const double* __r
         const double uv = Dinv[k] * rv;
         r[k] = rv;
         u[k] = uv;
-        x[k] = 0.0;
-        p[k] = 0.0;
-        s[k] = 0.0;
+        x[k] = 0.0;  // p and s are first written by iteration 0, which reads neither
         acc[0] += rv * uv;
         acc[1] += rv * rv;
     }
@@ -89,19 +87,38 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(
         return;
     }
     double acc[2] = {0.0, 0.0};
-    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
-         k += int64_t(gridDim.x) * kBlock) {
-        const double pk = u[k] + beta * p[k];
-        const double sk = w[k] + beta * s[k];
-        x[k] += alpha * pk;
-        const double rk = r[k] - alpha * sk;
-        const double uk = Dinv[k] * rk;
-        p[k] = pk;
-        s[k] = sk;
-        r[k] = rk;
-        u[k] = uk;
-        acc[0] += rk * uk;
-        acc[1] += rk * rk;
+    if (j == 0) {
+        // p = u, s = w, x = alpha p (x, p, s are zero before iteration 0,
+        // so this is the general update with the zero terms left out)
+        for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
+             k += int64_t(gridDim.x) * kBlock) {
+            const double pk = u[k];
+            const double sk = w[k];
+            x[k] = alpha * pk;
+            const double rk = r[k] - alpha * sk;
+            const double uk = Dinv[k] * rk;
+            p[k] = pk;
+            s[k] = sk;
+            r[k] = rk;
+            u[k] = uk;
+            acc[0] += rk * uk;
+            acc[1] += rk * rk;
+        }
+    } else {
+        for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
+             k += int64_t(gridDim.x) * kBlock) {
+            const double pk = u[k] + beta * p[k];
+            const double sk = w[k] + beta * s[k];
+            x[k] += alpha * pk;
+            const double rk = r[k] - alpha * sk;
+            const double uk = Dinv[k] * rk;
+            p[k] = pk;
+            s[k] = sk;
+            r[k] = rk;
+            u[k] = uk;
+            acc[0] += rk * uk;
+            acc[1] += rk * rk;
+        }
     }
     block_reduce_store<2>(acc, upd_next + blockIdx.x * 2);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
