@@ -38,10 +38,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_payload(int64_t m, int d, const 
         }
         s = group_sum<LPR>(s);
         const double nd = sqrt(s);
-        const bool inter = labels[i] != labels[j] && nd > 0.0;
         const double r = gamma * w[l];
+        const bool inter = labels[i] != labels[j] && nd > 0.0 && r >= kTinyRadius;
         if (gl == 0) {
-            const double2 v{inter ? r / nd : 0.0, 1.0 / r};
+            const double2 v{inter ? r / nd : 0.0, inter ? 1.0 / r : 0.0};
             ipay[epos[2 * l]] = v;
             ipay[epos[2 * l + 1]] = v;
         }

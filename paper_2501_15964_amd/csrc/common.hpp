@@ -12,6 +12,13 @@ constexpr int kMaxGrid = 2048;       // cap on grid-stride grids (partials per k
 // doubles in a partials buffer: two kernels of kMaxGrid blocks, up to 8 values each
 constexpr int kPartialsCap = 2 * kMaxGrid * 8;
 
+// Radius below which an l2 dual ball (q = 2) is taken as {0}: the projection
+// is 0 and its Jacobian 0.  The Newton payload carries 1/r and the matvec
+// a/r^2 (a <= 1), both finite for r >= 2^-500; r = gamma w falls below it when
+// a Gaussian weight of a far neighbour underflows, and the exact projection
+// differs from 0 by less than r there.
+constexpr double kTinyRadius = 0x1p-500;
+
 // q selector for the per-edge norm ||.||_q; the dual ball is in the q* norm.
 enum QKind : int { kQ1 = 1, kQ2 = 2, kQInf = 3 };
 

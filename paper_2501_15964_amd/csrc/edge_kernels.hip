@@ -20,7 +20,7 @@ __device__ __forceinline__ void store_payload(const RowProj<LPR, NPER, Q>& o, in
     if constexpr (Q == kQ1 || Q == kQInf) pl.lbits[l * LPR + gl] = o.lm;
     if (gl != 0) return;
     double2 v;
-    if constexpr (Q == kQ2) v = double2{o.alpha, 1.0 / r};
+    if constexpr (Q == kQ2) v = double2{o.alpha, o.alpha > 0.0 ? 1.0 / r : 0.0};
     else v = double2{double(o.cnt), 0.0};
     if constexpr (Q == kQ2 || Q == kQInf) {
         pl.ipay[epos[2 * l]] = v;

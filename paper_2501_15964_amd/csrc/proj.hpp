@@ -28,7 +28,11 @@ __device__ __forceinline__ void project_row(const double (&y)[NPER], int gl, int
         for (int t = 0; t < NPER; ++t) s += y[t] * y[t];
         s = group_sum<LPR>(s);
         const double nrm = sqrt(s);
-        if (nrm > r) {
+        if (!(r >= kTinyRadius)) {
+            o.alpha = 0.0;
+#pragma unroll
+            for (int t = 0; t < NPER; ++t) o.pi[t] = 0.0;
+        } else if (nrm > r) {
             const double a = r / nrm;
             o.alpha = a;
 #pragma unroll

@@ -541,7 +541,12 @@ __global__ __launch_bounds__(kBlock, edge_grad_min_waves<NPER>()) void k_edge_gr
 #pragma unroll
                         for (int t = 0; t < NPER; ++t) s2 += pi[t] * pi[t];
                         const double nrm = sqrt(group_sum<LPR>(s2));
-                        if (nrm > r) {
+                        if (!(r >= kTinyRadius)) {
+                            // a ball too small for 1/r: taken as {0}
+                            alpha = 0.0;
+#pragma unroll
+                            for (int t = 0; t < NPER; ++t) pi[t] = 0.0;
+                        } else if (nrm > r) {
                             alpha = r / nrm;
 #pragma unroll
                             for (int t = 0; t < NPER; ++t) pi[t] *= alpha;
@@ -556,7 +561,7 @@ __global__ __launch_bounds__(kBlock, edge_grad_min_waves<NPER>()) void k_edge_gr
 #pragma unroll
                     for (int t = 0; t < NPER; ++t) acc[t] += m.pos ? pi[t] : -pi[t];
                     if constexpr (Q == kQ2) {
-                        const double ir = 1.0 / r;
+                        const double ir = alpha > 0.0 ? 1.0 / r : 0.0;
                         if (alpha >= 1.0) {
 #pragma unroll
                             for (int t = 0; t < NPER; ++t) dg[t] += 1.0;

@@ -421,3 +421,72 @@ def test_qinf_tiny_weights_path():
     assert w.min() < 1e-30
     gammas = [1e-3, 1e-2]
     _compare_path(A, src, dst, w, gammas, np.inf, "ssnal", 1e-7, x_tol=1e-5)
+
+
+def _with_tiny_weights(w):
+    # Gaussian weights of far neighbours underflow: put subnormal, tiny and
+    # zero weights on a share of the edges (gamma w then falls below the
+    # radius at which 1/r stops being finite)
+    w = w.copy()
+    w[0::7] = 1e-310
+    w[1::11] = 5e-324
+    w[2::13] = 1e-200
+    w[3::17] = 0.0
+    return w
+
+
+def _tiny_weight_graph(seed=1601):
+    A, _ = synthdata.mixture64(n_per=60, d=2, n_blobs=5, seed=seed)
+    src, dst, w, *_ = oracle.knn_graph(A, 8, None)
+    return A, src, dst, _with_tiny_weights(w)
+
+
+@pytest.mark.parametrize("q", [2.0, 1.0, np.inf])
+def test_subnormal_and_tiny_weights(q):
+    torch, ccm = need_gpu()
+    A, src, dst, w = _tiny_weight_graph()
+    # the library drops the zero-weight edges (U has a row per kept edge)
+    keep = w > 0
+    B = oracle.incidence(src[keep], dst[keep], A.shape[0])
+    gammas = [1e-2, 0.2, 1.0]
+    for method in (0, 1, 3):
+        o = ccm.ccm_default_options(method=method)
+        out = ccm.ccm_solve_path(dev(A), *graph_dev(src, dst, w), gammas, q, 1e-8, opts=o,
+                                 want_U=True)
+        for t, g in enumerate(gammas):
+            assert int(out["status"][t]) == 0, (method, t)
+            X, U = host(out["X"][t]), host(out["U"][t])
+            assert np.all(np.isfinite(X)) and np.all(np.isfinite(U))
+            bound, res = oracle.operators.distance_bound(X, U, A, B, g * w[keep], q)
+            assert res["kkt"] <= 1e-8 * 1.0001, (method, t, res)
+            assert bound <= 1e-5 * np.linalg.norm(X), (method, t, bound)
+
+
+def test_vjp_with_tiny_weights():
+    torch, ccm = need_gpu()
+    A, src, dst, w, T = _adjoint_problem(seed=1602)
+    w = _with_tiny_weights(w)
+    keep = w > 0  # the adjoint takes canonical edges (w > 0)
+    src, dst, w = src[keep], dst[keep], w[keep]
+    n = A.shape[0]
+    S = oracle.fusion_scale(A)
+    # (an edge of negligible weight has no dual slack; the labels do not
+    # depend on its margin)
+    big = w > 1e-100
+    for g in (0.08, 0.15, 0.3):
+        Xo, Uo, _, _ = oracle.ssnal(A, src, dst, w, g, 2.0, 1e-12)
+        lab, K = oracle.cluster_labels(Xo, src, dst, n, S)
+        mg = oracle.fusion_margins(Xo, Uo, src, dst, w, g, 2.0, S)
+        if 1 < K < n and mg[big].min() > 1e-3:
+            break
+    assert 1 < K < n and mg[big].min() > 1e-3
+    out = ccm.ccm_solve_path(dev(A), *graph_dev(src, dst, w), [g], 2.0, 1e-11)
+    X = out["X"][0]
+    assert np.array_equal(host(out["labels"][0]), lab)
+    dA, dlw, dg, _ = ccm.ccm_path_vjp(dev(A), *graph_dev(src, dst, w), g, X, out["labels"][0],
+                                      dev(2 * (host(X) - T)), tol=1e-13)
+    rA, rlw, rg = oracle.path_vjp(A, src, dst, w, g, Xo, 2 * (Xo - T), labels=lab)
+    assert np.all(np.isfinite(host(dA))) and np.all(np.isfinite(host(dlw)))
+    assert rel(host(dA), rA) <= 1e-6
+    assert rel(host(dlw), rlw) <= 1e-6
+    assert abs(dg - rg) <= 1e-6 * (1 + abs(rg))
