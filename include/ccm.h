@@ -110,6 +110,11 @@ typedef struct {
                               captured once per call (same kernels, bit-identical
                               results, fewer launches); 0 (default): plain launches.
                               Not used while profile != 0 */
+    int32_t window_chunk;  /* incidences per row group of a vertex-kernel window; 0
+                              (default): the tuned value for the row width and q (a table
+                              the package's window tuner writes); changes the summation
+                              order of split vertices, so results depend on it (each value
+                              deterministic) */
 } ccm_options;
 
 ccm_options ccm_default_options(void);

@@ -23,10 +23,12 @@ __all__ = [
     "ccm_op_scatter", "ccm_op_hess_matvec", "ccm_kkt", "ccm_labels", "ccm_stream_copy",
     "ccm_path_vjp", "CCMSolve", "ccm_solve_path_batched", "CcmInstance", "EXPORTED_SYMBOLS",
     "ccm_build_knn_graph_u8", "ccm_release_workspace", "ccm_labels_noalloc",
-    "ccm_weights_from_log", "CCM_E_NOT_CONVERGED",
+    "ccm_weights_from_log", "CCM_OK", "CCM_E_INVALID", "CCM_E_UNSUPPORTED", "CCM_E_HIP",
+    "CCM_E_NOMEM", "CCM_E_CAPACITY", "CCM_E_NOT_CONVERGED",
 ]
 
-CCM_E_NOT_CONVERGED = 6
+(CCM_OK, CCM_E_INVALID, CCM_E_UNSUPPORTED, CCM_E_HIP, CCM_E_NOMEM, CCM_E_CAPACITY,
+ CCM_E_NOT_CONVERGED) = range(7)
 
 CCM_SSNAL, CCM_ADMM, CCM_AMA, CCM_HPR = 0, 1, 2, 3
 CCM_CONVERGED, CCM_MAX_ITER, CCM_TIMEOUT, CCM_NUMERICAL = 0, 1, 2, 3
@@ -60,6 +62,7 @@ class CcmOptions(ctypes.Structure):
         ("sigma0", ctypes.c_double), ("sigma_max", ctypes.c_double),
         ("tau", ctypes.c_double), ("time_budget_s", ctypes.c_double),
         ("locality", ctypes.c_int32), ("graphs", ctypes.c_int32),
+        ("window_chunk", ctypes.c_int32),
     ]
 
 

@@ -212,7 +212,7 @@ ccm_status solve_group(const ccm_instance* inst_host, const std::vector<int>& id
     std::string err;
     OwnedGraph og;
     st = graph_build(su.as<int>(), du.as<int>(), wu.as<double>(), mU, nU, d, true, stream, og,
-                     err, o.locality);
+                     err, o.locality, qk, o.window_chunk);
     if (st != CCM_OK) return fail(st, err);
     Solver solver(og.g, d, qk, Au.as<double>(), stream, o, tol, err);
     st = solver.run_batched(gammas_host, n_gamma, b);
@@ -342,12 +342,15 @@ ccm_status ccm_solve_path(const double* A, int64_t n, int64_t d, const int32_t* 
     if (o.sigma0 <= 0) o.sigma0 = 1.0;
     if (!(o.sigma_max >= o.sigma0)) o.sigma_max = o.sigma0;
     if (!(o.tau > 0 && o.tau < 1.6181)) return fail(CCM_E_INVALID, "tau must be in (0, 1.618]");
+    if (o.window_chunk < 0 || o.window_chunk > 4096)
+        return fail(CCM_E_INVALID, "window_chunk must be in [0, 4096]");
     st = check_finite(A, n * d, stream, "A");
     if (st != CCM_OK) return st;
     if (n_gamma == 0) return CCM_OK;
     std::string err;
     OwnedGraph og;
-    st = graph_build(src, dst, w, m, n, int(d), false, stream, og, err, o.locality);
+    st = graph_build(src, dst, w, m, n, int(d), false, stream, og, err, o.locality, qk,
+                     o.window_chunk);
     if (st != CCM_OK) return fail(st, err);
     Solver solver(og.g, int(d), qk, A, stream, o, tol, err);
     st = solver.run_path(gammas_host, n_gamma, X_warm, U_warm, X_out, U_out, labels_out,
@@ -377,6 +380,8 @@ ccm_status ccm_solve_path_batched(const ccm_instance* inst_host, int32_t n_inst,
     o.method = CCM_SSNAL;
     if (o.max_outer < 1 || o.max_newton < 1 || o.cg_max_iter < 1)
         return fail(CCM_E_INVALID, "iteration limits must be >= 1");
+    if (o.window_chunk < 0 || o.window_chunk > 4096)
+        return fail(CCM_E_INVALID, "window_chunk must be in [0, 4096]");
     if (o.sigma0 <= 0) o.sigma0 = 1.0;
     if (!(o.sigma_max >= o.sigma0)) o.sigma_max = o.sigma0;
     // group instances by (q, d)

@@ -604,7 +604,7 @@ ccm_status locality_order(OwnedGraph& out, hipStream_t s, std::string& err) {
 
 ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t m, int64_t n,
                        int d, bool require_canonical, hipStream_t s, OwnedGraph& out,
-                       std::string& err, int locality) {
+                       std::string& err, int locality, int qk, int chunk) {
     if (n < 1 || n > (int64_t(1) << 30) || m < 0 || m > (int64_t(1) << 30)) {
         err = "graph size out of range";
         return CCM_E_INVALID;
@@ -672,10 +672,11 @@ ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t 
         st = locality_order(out, s, err);
         if (st != CCM_OK) return st;
     }
-    return build_windows(d, s, out, err);
+    return build_windows(d, s, out, err, qk, chunk);
 }
 
-ccm_status build_windows(int d, hipStream_t s, OwnedGraph& out, std::string& err) {
+ccm_status build_windows(int d, hipStream_t s, OwnedGraph& out, std::string& err, int qk,
+                         int chunk) {
     // Vertex-aligned windows of the incidence array, packed greedily on the
     // host: consecutive whole vertices while the window holds at most S
     // entries; a vertex with more than S entries (a hub) forms a window of
@@ -686,7 +687,7 @@ ccm_status build_windows(int d, hipStream_t s, OwnedGraph& out, std::string& err
         err = "internal: incidence lists incomplete (entries, vertex ids or offsets missing)";
         return CCM_E_HIP;
     }
-    const int64_t S = window_for(d);
+    const int64_t S = window_for(d, qk, chunk);
     std::vector<int> ptr(size_t(n) + 1), vord;
     HIPCHK(hipMemcpyAsync(ptr.data(), out.g.inc_ptr, ptr.size() * 4, hipMemcpyDeviceToHost, s));
     if (out.g.vord) {

@@ -56,14 +56,17 @@ struct OwnedGraph {
 // vertices the vertex kernels work on at the same time (and so what the
 // caches hold), never the data layout.  Returns CCM_OK or an error with text
 // in `err`.  Synchronises s.
+// The windows hold window_for(d, qk, chunk) incidences (chunk <= 0: the
+// tuned chunk of d's row layout and q).
 constexpr int64_t kLocalityMin = int64_t(1) << 22;
 ccm_status graph_build(const int* src, const int* dst, const double* w, int64_t m, int64_t n,
                        int d, bool require_canonical, hipStream_t s, OwnedGraph& out,
-                       std::string& err, int locality = -1);
+                       std::string& err, int locality = -1, int qk = kQ2, int chunk = 0);
 
 // Window split (win, iso) of out.g's incidence lists for rows of d values;
 // needs out.g.n, nent, inc_ptr, inc, irow.  Synchronises s.
-ccm_status build_windows(int d, hipStream_t s, OwnedGraph& out, std::string& err);
+ccm_status build_windows(int d, hipStream_t s, OwnedGraph& out, std::string& err,
+                         int qk = kQ2, int chunk = 0);
 
 // Cluster membership lists as a graph for the vertex kernels: row c lists
 // the vertices with labels == c (labels in [0, K)), entries {vertex, 0}.

@@ -6,6 +6,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "tuned_windows.hpp"
 
 namespace ccm {
 
@@ -125,12 +126,27 @@ inline size_t partials_for(const DevGraph& g) {
     return need > size_t(kPartialsCap) ? need : size_t(kPartialsCap);
 }
 
-// incidences per row group of a window: about one typical vertex for long
-// rows, several short vertices for short rows
-inline int chunk_for(int d) { return d <= 64 ? 16 : d <= 256 ? 32 : 64; }
+// index of d's row layout in dispatch_row's order
+inline int layout_index(int d) {
+    static constexpr int kMaxD[] = {2, 4, 8, 16, 32, 64, 128, 256, 512, 768, 832, 1024};
+    int i = 0;
+    while (i + 1 < kTunedLayouts && d > kMaxD[i]) ++i;
+    return i;
+}
+
+// incidences per row group of a window (about one typical vertex for long
+// rows, several short vertices for short rows): `chunk` if positive, else the
+// tuned value for d's row layout and q (qk = kQ1, kQ2 or kQInf)
+inline int chunk_for(int d, int qk = kQ2, int chunk = 0) {
+    if (chunk > 0) return chunk;
+    const int qi = qk == kQ1 ? 0 : qk == kQInf ? 2 : 1;
+    return kTunedChunk[layout_index(d)][qi];
+}
 
 // target entries per window: one chunk for each row group of a workgroup
-inline int64_t window_for(int d) { return int64_t(kBlock / lanes_per_row(d)) * chunk_for(d); }
+inline int64_t window_for(int d, int qk = kQ2, int chunk = 0) {
+    return int64_t(kBlock / lanes_per_row(d)) * chunk_for(d, qk, chunk);
+}
 
 // ---- edge kernels (edge_kernels.hip) --------------------------------------
 // SSNAL edge pass: Y = U + sigma B X, Pi = Pi_C(Y), payload; partials per

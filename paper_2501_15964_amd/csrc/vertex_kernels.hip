@@ -70,8 +70,10 @@ __device__ __forceinline__ Meta load_meta(const DevGraph& g, int64_t p, const Pa
     return m;
 }
 
-// Row-group share of each row layout (the host's chunk_for(d) for the d the
-// layout serves).
+// Row-group share that a layout's incidence prefetch is sized for (the
+// window chunk before the window table was tuned); a row group with a longer
+// share loads its incidence data in several rounds, one with a shorter share
+// leaves slots empty.
 template <int LPR, int NPER>
 constexpr int chunk_of() {
     return LPR * NPER <= 64 ? 16 : LPR * NPER <= 256 ? 32 : 64;

@@ -65,3 +65,11 @@ def test_status_codes_named():
     L = ccm.lib()
     assert L.ccm_status_string(ccm.CCM_E_NOT_CONVERGED).decode() != "unknown status"
     assert ccm.CCM_E_NOT_CONVERGED == 6
+
+
+def test_status_codes_match_header():
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "ccm.h")).read()
+    for name, val in re.findall(r"\b(CCM_(?:OK|E_[A-Z_]+))\s*=\s*(\d+)", hdr):
+        assert getattr(ccm, name) == int(val), name

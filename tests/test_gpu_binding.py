@@ -54,3 +54,34 @@ def test_batched_labels_use_each_instance_scale():
             assert np.array_equal(host(res[k]["labels"][t]), host(single["labels"][t])), (k, t)
             assert res[k]["n_clusters"][t] == single["n_clusters"][t]
     assert res[0]["n_clusters"][0] > 1
+
+
+@pytest.mark.parametrize("d,q", [(12, 2.0), (100, 1.0), (300, np.inf)])
+def test_window_chunk_changes_rounding_only(d, q):
+    # the window size decides how vertices are cut between row groups, so
+    # only the summation order of cut vertices changes: every chunk must
+    # reach a solution the oracle certifies, with the same clusters
+    torch, ccm = need_gpu()
+    from paper_2501_15964_amd.ccm import CcmError
+    A, _ = synthdata.mixture64(n_per=80, d=d, n_blobs=4, seed=4010 + d)
+    src, dst, w, *_ = oracle.knn_graph(A, 6, None)
+    gd = graph_dev(src, dst, w)
+    g = 0.05 if q != np.inf else 0.2
+    B = oracle.incidence(src, dst, A.shape[0])
+    runs = {}
+    for chunk in (0, 1, 8, 128, 4096):
+        o = ccm.ccm_default_options(window_chunk=chunk)
+        out = ccm.ccm_solve_path(dev(A), *gd, [g], q, 1e-9, opts=o, want_U=True)
+        assert int(out["status"][0]) == 0, chunk
+        X, U = host(out["X"][0]), host(out["U"][0])
+        bound, res = oracle.operators.distance_bound(X, U, A, B, g * w, q)
+        assert res["kkt"] <= 1e-9 * 1.0001, (chunk, res)
+        assert bound <= 1e-6 * np.linalg.norm(X), (chunk, bound)
+        runs[chunk] = (X, host(out["labels"][0]))
+    for chunk, (X, lab) in runs.items():
+        np.testing.assert_allclose(X, runs[0][0], rtol=0, atol=4e-6 * np.abs(A).max())
+        assert np.array_equal(lab, runs[0][1]), chunk
+    with pytest.raises(CcmError) as ex:
+        ccm.ccm_solve_path(dev(A), *gd, [g], q, 1e-6,
+                           opts=ccm.ccm_default_options(window_chunk=4097))
+    assert ex.value.status == ccm.CCM_E_INVALID
