@@ -109,12 +109,22 @@ typedef struct {
     int32_t graphs;        /* 1: CG iterations are replayed two at a time from HIP graphs
                               captured once per call (same kernels, bit-identical
                               results, fewer launches); 0 (default): plain launches.
-                              Not used while profile != 0 */
+                              Not used while profile != 0, nor by
+                              ccm_solve_path_batched (whose groups run concurrently
+                              from several host threads) */
     int32_t window_chunk;  /* incidences per row group of a vertex-kernel window; 0
                               (default): the tuned value for the row width and q (a table
                               the package's window tuner writes); changes the summation
                               order of split vertices, so results depend on it (each value
                               deterministic) */
+    int32_t dual_scale;    /* SSNAL path continuation.  1: before each gamma after the
+                              first, the rows of U on the boundary of the previous gamma's
+                              dual balls (q = 1: the coordinates at +-r) are scaled by
+                              gamma_t / gamma_{t-1}: the dual of an edge whose endpoints are
+                              apart is gamma w_l times a direction that moves slowly along
+                              the path.  0: (X, U) carried over unchanged.  -1 (default):
+                              1 for q = 2, 0 otherwise (measured faster, resp. slower).
+                              Only the starting point changes, not the solution */
 } ccm_options;
 
 ccm_options ccm_default_options(void);

@@ -81,6 +81,7 @@ ccm_options defaults() {
     o.time_budget_s = 0.0;
     o.locality = -1;
     o.graphs = 0;
+    o.dual_scale = -1;
     return o;
 }
 
@@ -344,6 +345,8 @@ ccm_status ccm_solve_path(const double* A, int64_t n, int64_t d, const int32_t* 
     if (!(o.tau > 0 && o.tau < 1.6181)) return fail(CCM_E_INVALID, "tau must be in (0, 1.618]");
     if (o.window_chunk < 0 || o.window_chunk > 4096)
         return fail(CCM_E_INVALID, "window_chunk must be in [0, 4096]");
+    if (o.dual_scale < -1 || o.dual_scale > 1)
+        return fail(CCM_E_INVALID, "dual_scale must be -1, 0 or 1");
     st = check_finite(A, n * d, stream, "A");
     if (st != CCM_OK) return st;
     if (n_gamma == 0) return CCM_OK;
@@ -382,6 +385,8 @@ ccm_status ccm_solve_path_batched(const ccm_instance* inst_host, int32_t n_inst,
         return fail(CCM_E_INVALID, "iteration limits must be >= 1");
     if (o.window_chunk < 0 || o.window_chunk > 4096)
         return fail(CCM_E_INVALID, "window_chunk must be in [0, 4096]");
+    if (o.dual_scale < -1 || o.dual_scale > 1)
+        return fail(CCM_E_INVALID, "dual_scale must be -1, 0 or 1");
     if (o.sigma0 <= 0) o.sigma0 = 1.0;
     if (!(o.sigma_max >= o.sigma0)) o.sigma_max = o.sigma0;
     // group instances by (q, d)

@@ -376,6 +376,42 @@ __global__ __launch_bounds__(kBlock) void k_project(int64_t m, int d, const doub
     }
 }
 
+// Path continuation of the dual: the rows of U that lie on the boundary of
+// their ball of radius g0 w_l are scaled by rho (q = 1: the coordinates at
+// +-g0 w_l, the box being a product of intervals).  A row on the boundary
+// belongs to an edge whose endpoints are apart, and there u_l is g0 w_l times
+// a unit direction that moves slowly with gamma.
+template <int LPR, int NPER, int Q>
+__global__ __launch_bounds__(kBlock) void k_scale_boundary(int64_t m, int d,
+                                                           const double* __restrict__ w,
+                                                           double g0, double rho,
+                                                           double* __restrict__ U) {
+    constexpr int GPB = kBlock / LPR;
+    const int gl = (threadIdx.x & 63) % LPR;
+    for (int64_t l = int64_t(blockIdx.x) * GPB + threadIdx.x / LPR; l < m;
+         l += int64_t(gridDim.x) * GPB) {
+        const double edge = (1.0 - 1e-9) * g0 * w[l];
+        double u[NPER];
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            u[t] = (k < d) ? U[l * d + k] : 0.0;
+            if constexpr (Q == kQ2) s += u[t] * u[t];
+            else if constexpr (Q == kQInf) s += fabs(u[t]);
+        }
+        bool row = false;
+        if constexpr (Q == kQ2) row = sqrt(group_sum<LPR>(s)) >= edge;
+        else if constexpr (Q == kQInf) row = group_sum<LPR>(s) >= edge;
+#pragma unroll
+        for (int t = 0; t < NPER; ++t) {
+            const int k = gl + LPR * t;
+            const bool on = Q == kQ1 ? fabs(u[t]) >= edge : row;
+            if (k < d && on) U[l * d + k] = u[t] * rho;
+        }
+    }
+}
+
 template <int LPR, int NPER>
 __global__ __launch_bounds__(kBlock) void k_fused_flags(int64_t m, int d,
                                                         const int* __restrict__ src,
@@ -504,6 +540,19 @@ void launch_project(int64_t m, int d, int qk, const double* Y, const double* w, 
             constexpr int q = decltype(Qc)::value;
             hipLaunchKernelGGL((k_project<lpr, nper, q>), dim3(row_grid(m, lpr)), dim3(kBlock), 0,
                                s, m, d, Y, w, gamma, prox ? 1 : 0, out);
+        });
+    });
+}
+
+void launch_scale_boundary(int64_t m, int d, int qk, const double* w, double g0, double rho,
+                           double* U, hipStream_t s) {
+    if (m <= 0) return;
+    dispatch_row(d, [&](auto L, auto N) {
+        constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
+        dispatch_q(qk, [&](auto Qc) {
+            constexpr int q = decltype(Qc)::value;
+            hipLaunchKernelGGL((k_scale_boundary<lpr, nper, q>), dim3(row_grid(m, lpr)),
+                               dim3(kBlock), 0, s, m, d, w, g0, rho, U);
         });
     });
 }

@@ -193,6 +193,10 @@ int launch_edge_ama(const DevGraph& g, int d, int qk, double gamma, double nu, d
 void launch_gather(const DevGraph& g, int d, const double* X, double* Y, hipStream_t s);
 void launch_project(int64_t m, int d, int qk, const double* Y, const double* w, double gamma,
                     bool prox, double* out, hipStream_t s);
+// U rows (q = 1: coordinates) on the boundary of their ball of radius g0 w_l
+// are multiplied by rho
+void launch_scale_boundary(int64_t m, int d, int qk, const double* w, double g0, double rho,
+                           double* U, hipStream_t s);
 // fused[l] = ||x_src - x_dst||_2 <= thr; with `spread` (a device scalar S)
 // the threshold is 1e-5 (1 + S) instead of thr; with `vthr` (per vertex) it is
 // vthr[src_l]

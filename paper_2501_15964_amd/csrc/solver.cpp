@@ -377,6 +377,16 @@ struct Solver::Impl {
         nfin = 0;
     }
 
+    // SSNAL path continuation (ccm_options.dual_scale): before a new gamma,
+    // the multiplier rows on the boundary of the previous gamma's balls are
+    // moved to the new radii
+    void continue_dual(double g_prev, double g_new) {
+        const bool on = o.dual_scale > 0 || (o.dual_scale < 0 && qk == kQ2);
+        if (!on || !have_U || M == 0 || !(g_prev > 0.0) || !(g_new > 0.0) || g_new == g_prev)
+            return;
+        launch_scale_boundary(m, d, qk, g.w, g_prev, g_new / g_prev, U, s);
+    }
+
     bool out_of_time() const {
         if (!(o.time_budget_s > 0)) return false;
         const double el = std::chrono::duration<double>(Clock::now() - t_start).count();
@@ -506,7 +516,10 @@ struct Solver::Impl {
     };
     std::vector<CgGraph> graphs;
     hipStream_t cap_stream = nullptr;
-    bool use_graphs() const { return o.graphs != 0 && !prof.on; }
+    // Not in the batched form: its groups run from a pool of host threads,
+    // and a capture on one thread while another allocates work space failed
+    // there with a capture-isolation error.
+    bool use_graphs() const { return o.graphs != 0 && !prof.on && !batch; }
 
     ccm_status cg_graph(hipGraphExec_t& out) {
         for (const auto& gk : graphs)
@@ -1268,6 +1281,7 @@ ccm_status Solver::run_path(const double* gammas, int T, const double* Xw, const
             // the penalty restarts at sigma0 for every gamma: a penalty grown
             // on one problem makes the next, more fused one ill-conditioned
             I.sigma = I.o.sigma0;
+            if (t > 0) I.continue_dual(gammas[t - 1], gamma);
             CHK(I.ssnal(gamma, stat, st, res));
         } else if (I.o.method == CCM_ADMM) {
             CHK(I.admm(gamma, stat, st, res));
@@ -1355,6 +1369,7 @@ ccm_status Solver::run_batched(const double* gammas, int T, const BatchSpec& b) 
             I.inst_res.assign(S, {0, 0, 0, 0, 0, 0, 0});
         } else {
             I.sigma = I.o.sigma0;
+            if (t > 0) I.continue_dual(gammas[t - 1], gamma);
             CHK(I.ssnal(gamma, stat, st, res));
         }
         int ncl = 0;

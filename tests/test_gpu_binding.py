@@ -85,3 +85,52 @@ def test_window_chunk_changes_rounding_only(d, q):
         ccm.ccm_solve_path(dev(A), *gd, [g], q, 1e-6,
                            opts=ccm.ccm_default_options(window_chunk=4097))
     assert ex.value.status == ccm.CCM_E_INVALID
+
+
+@pytest.mark.parametrize("q", [2.0, 1.0, np.inf])
+def test_dual_scale_changes_the_start_only(q):
+    # scaling the boundary duals between gammas (up and down the path) must
+    # reach the same unique X* as the plain warm start: both are compared with
+    # oracle solves whose own distance to X* the duality gap bounds
+    torch, ccm = need_gpu()
+    A, _ = synthdata.mixture64(n_per=60, d=6, n_blobs=4, seed=4020)
+    src, dst, w, *_ = oracle.knn_graph(A, 6, None)
+    gd = graph_dev(src, dst, w)
+    B = oracle.incidence(src, dst, A.shape[0])
+    gammas = [0.01, 0.05, 0.2, 0.05, 1.0, 3.0]
+    runs = {}
+    for ds in (0, 1):
+        o = ccm.ccm_default_options(dual_scale=ds)
+        out = ccm.ccm_solve_path(dev(A), *gd, gammas, q, 1e-11, opts=o, want_U=True)
+        assert np.all(out["status"] == 0), ds
+        runs[ds] = out
+    for t, g in enumerate(gammas):
+        Xo, Uo, _, _ = oracle.ssnal(A, src, dst, w, g, q, 1e-11)
+        bo, _ = oracle.operators.distance_bound(Xo, Uo, A, B, g * w, q)
+        nXo = np.linalg.norm(Xo)
+        assert bo <= 1e-6 * nXo, (t, bo)
+        for ds in (0, 1):
+            X, U = host(runs[ds]["X"][t]), host(runs[ds]["U"][t])
+            res = oracle.operators.kkt_residuals(X, U, A, B, g * w, q)
+            assert res["kkt"] <= 1e-11 * 1.0001, (ds, t, res)
+            assert np.linalg.norm(X - Xo) <= 1e-5 * nXo, (ds, t)
+        assert np.array_equal(host(runs[1]["labels"][t]), host(runs[0]["labels"][t])), t
+
+
+def test_dual_scale_in_batched_groups():
+    torch, ccm = need_gpu()
+    insts = synthdata.instances(seed=4021, count=6, n_lo=40, n_hi=120, dims=(2, 8),
+                                blobs_lo=2, blobs_hi=4)
+    devs = []
+    for it in insts:
+        src, dst, w, *_ = oracle.knn_graph(it["A"], 5, None)
+        devs.append(dict(A=dev(it["A"]), src=dev(src.astype(np.int32)),
+                         dst=dev(dst.astype(np.int32)), w=dev(w), q=it["q"]))
+    g = synthdata.gamma_grid(-2, 0.5, 4)
+    a = ccm.ccm_solve_path_batched(devs, g, 1e-10, opts=ccm.ccm_default_options(dual_scale=1))
+    b = ccm.ccm_solve_path_batched(devs, g, 1e-10, opts=ccm.ccm_default_options(dual_scale=0))
+    for ra, rb, it in zip(a, b, insts):
+        assert np.all(ra["status"] == 0) and np.all(rb["status"] == 0)
+        for t in range(len(g)):
+            np.testing.assert_allclose(host(ra["X"][t]), host(rb["X"][t]), rtol=0,
+                                       atol=1e-5 * np.abs(it["A"]).max())

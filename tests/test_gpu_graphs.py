@@ -42,7 +42,9 @@ def test_graph_replay_matches_plain_launches(q, method):
     assert sum(st["cg"] for st in runs[0]["stats"]) > 20  # many replays
 
 
-def test_graph_replay_in_batched_groups():
+def test_batched_groups_accept_the_graph_option():
+    # the batched form runs plain launches whatever the option says (its
+    # groups capture-free, see ccm_options.graphs): results bit-identical
     torch, ccm = need_gpu()
     insts = synthdata.instances(seed=1502, count=8, n_lo=40, n_hi=120, dims=(2, 8),
                                 blobs_lo=2, blobs_hi=4)
