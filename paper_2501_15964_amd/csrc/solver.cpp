@@ -530,7 +530,9 @@ struct Solver::Impl {
             }
         if (!cap_stream) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
         CgGraph gk{cr.mode, cr.Dv, cr.Pic, cr.p.ipay, cr.p.lbits};
-        HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+        // relaxed: the capture holds kernel launches only, and no other call
+        // of this or another thread is to be refused while it is open
+        HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed));
         for (int par = 1; par >= 0; --par) {
             launch_cg_update_dev(N, par, cr.Dv, cg, cap_stream);
             CgSkip sk;
@@ -750,6 +752,10 @@ struct Solver::Impl {
 
     ccm_status ssnal(double gamma, int& status, ccm_stats& st, double (&res)[7]) {
         const double mu = 1e-4, ls_slack = 1e-14;
+        // first trial step of a line search: for q = 1 and inf twice the last
+        // accepted step, at most 1 (their semismooth steps are often halved
+        // several times in a row); for q = 2 always the full step
+        double a0 = 1.0;
         // inner Newton stop: gradient norm below this fraction of R_P (q = inf
         // takes a looser inner solve and a slower penalty growth, below)
         const double inner = qk == kQInf ? 0.5 : 0.2;
@@ -794,7 +800,7 @@ struct Solver::Impl {
                     cg_begin(0, G, true, Dinv, thr, gamma, Pi, pl);
                 }
                 CHK(cg_issue(cr.P[0], cg_first(0) + 2));
-                trial_eval(1.0, gamma);
+                trial_eval(a0, gamma);
                 CHK(read(kT, kST + kScatterNV, false));
                 if (cr.P[0].hf[0]) {
                     iters = cr.P[0].hf[1];
@@ -809,13 +815,13 @@ struct Solver::Impl {
                     prof.harvest();
                     CHK(cg_issue(cr.P[1], cg_later()));
                     CHK(cg_wait(1, iters));
-                    trial_eval(1.0, gamma);
+                    trial_eval(a0, gamma);
                     CHK(read(kT, kST + kScatterNV));
                 }
                 st.cg += iters;
                 st.newton++;
                 // Armijo backtracking on phi
-                double alpha = 1.0;
+                double alpha = a0;
                 bool accepted = false;
                 Ev evt;
                 for (int t = 0; t < 40; ++t) {
@@ -842,6 +848,7 @@ struct Solver::Impl {
                     alpha *= 0.5;
                 }
                 (void)accepted;  // after 40 halvings the last (tiny) step is taken
+                if (qk != kQ2) a0 = std::min(1.0, 2.0 * alpha);
                 std::swap(X, Xt);
                 std::swap(Pi, Pit);
                 std::swap(pl, plt);
