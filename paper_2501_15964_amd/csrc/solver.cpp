@@ -419,14 +419,15 @@ struct Solver::Impl {
 
     // ---- shared pieces -------------------------------------------------------
     // The SSNAL edge pass (Pi, payload, merit terms) and the gradient G with
-    // the Jacobi diagonal.  q = 1, 2: one vertex-centric launch in which both
-    // endpoints of an edge project its row (a clamp or a scaling).  q = inf:
-    // the edge-parallel pass then the vertex scatter, since its l1-ball
-    // projection (an iteration) costs more twice than Pi's extra read.
+    // the Jacobi diagonal.  q = 1, 2, and q = inf on rows of more than 256
+    // values: one vertex-centric launch in which both endpoints of an edge
+    // project its row.  q = inf on shorter rows: the edge-parallel pass then
+    // the vertex scatter, since there its l1-ball projection (an iteration)
+    // costs more twice than Pi's extra read.
     void edge_grad(const double* Xc, double* Pic, Payload p, double gamma, double* Gc, double* Dc,
                    double* epart, double* spart, int eslot, int sslot) {
         Timed t(prof, CCM_K_EDGE);
-        if (qk != kQInf) {
+        if (qk != kQInf || d > 256) {
             const int gp = launch_edge_grad(g, d, qk, gamma, sigma, Xc, U, A, Pic, p, Gc, Dc,
                                             epart, spart, s);
             defer_finalize(epart, gp, kEdgeSsnalNV, slot(eslot), s);

@@ -428,7 +428,7 @@ __global__ __launch_bounds__(kBlock, edge_grad_min_waves<NPER>()) void k_edge_gr
                                                           double* __restrict__ epart,
                                                           double* __restrict__ spart,
                                                           double* __restrict__ kpart) {
-    static_assert(Q == kQ1 || Q == kQ2, "the fused edge pass serves q = 1 and q = 2");
+    static_assert(!KKT || Q == kQ1 || Q == kQ2, "the fused KKT terms serve q = 1 and q = 2");
     constexpr int UB = EdgeGradUnroll<NPER>::U;
     constexpr int NM = meta_slots<LPR, NPER>();
     constexpr bool PF = NM <= 4;
@@ -535,10 +535,19 @@ __global__ __launch_bounds__(kBlock, edge_grad_min_waves<NPER>()) void k_edge_gr
                     }
                     // projection onto the dual ball in place (the same
                     // arithmetic as project_row): q = 2 scales by
-                    // min(1, r / ||y||), q = 1 clamps to [-r, r]
+                    // min(1, r / ||y||), q = 1 clamps to [-r, r], q = inf
+                    // projects onto the l1 ball (project_row itself)
                     double alpha = 1.0;
                     uint32_t lm = 0u;
-                    if constexpr (Q == kQ2) {
+                    int cnt = -1;
+                    if constexpr (Q == kQInf) {
+                        RowProj<LPR, NPER, kQInf> o;
+                        project_row<LPR, NPER, kQInf, true>(pi, gl, lane, d, r, o);
+#pragma unroll
+                        for (int t = 0; t < NPER; ++t) pi[t] = o.pi[t];
+                        cnt = o.cnt;
+                        lm = o.lm;
+                    } else if constexpr (Q == kQ2) {
                         double s2 = 0.0;
 #pragma unroll
                         for (int t = 0; t < NPER; ++t) s2 += pi[t] * pi[t];
@@ -575,6 +584,18 @@ __global__ __launch_bounds__(kBlock, edge_grad_min_waves<NPER>()) void k_edge_gr
                             }
                         }
                         if (gl == 0) pl.ipay[p0 + u] = double2{alpha, ir};
+                    } else if constexpr (Q == kQInf) {
+                        // P = I inside; diag(1_S) - s_S s_S^T / |S| outside
+                        if (cnt < 0) {
+#pragma unroll
+                            for (int t = 0; t < NPER; ++t) dg[t] += 1.0;
+                        } else if (cnt > 0) {
+                            const double f = 1.0 - 1.0 / double(cnt);
+#pragma unroll
+                            for (int t = 0; t < NPER; ++t)
+                                if ((lm >> t) & 1u) dg[t] += f;
+                        }
+                        if (gl == 0) pl.ipay[p0 + u] = double2{double(cnt), 0.0};
                     } else {
 #pragma unroll
                         for (int t = 0; t < NPER; ++t)
@@ -597,6 +618,7 @@ __global__ __launch_bounds__(kBlock, edge_grad_min_waves<NPER>()) void k_edge_gr
                         if constexpr (Q != kQ2) pl.lbits[l * LPR + gl] = lm;
                         if (gl == 0) {
                             if constexpr (Q == kQ2) eacc[4] += (alpha < 1.0) ? 1.0 : 0.0;
+                            else if constexpr (Q == kQInf) eacc[4] += (cnt >= 0) ? 1.0 : 0.0;
                             else eacc[4] += 1.0;
                         }
                         if constexpr (KKT) {
@@ -994,7 +1016,17 @@ int launch_edge_grad(const DevGraph& g, int d, int qk, double gamma, double sigm
             if (kpart) go(IC<kQ2>{}, IC<1>{});
             else go(IC<kQ2>{}, IC<0>{});
         } else {
-            total = -1;  // q = inf has no fused pass (the caller runs two kernels)
+            // q = inf: whole-wave rows only (at shorter rows the two
+            // edge-parallel kernels were faster than projecting at both
+            // endpoints), and without the KKT terms
+            if constexpr (lpr == 64) {
+                if (!kpart) {
+                    go(IC<kQInf>{}, IC<0>{});
+                    total = g1;
+                    return;
+                }
+            }
+            total = -1;
             return;
         }
         total = g1;

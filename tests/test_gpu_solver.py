@@ -490,3 +490,22 @@ def test_vjp_with_tiny_weights():
     assert rel(host(dA), rA) <= 1e-6
     assert rel(host(dlw), rlw) <= 1e-6
     assert abs(dg - rg) <= 1e-6 * (1 + abs(rg))
+
+
+@pytest.mark.parametrize("q", [np.inf, 2.0])
+def test_long_rows_with_a_hub(q):
+    # rows of 300 values (q = inf takes the fused edge pass there) on a graph
+    # whose hub has more incidences than a window holds (at most 256 here)
+    rng = np.random.default_rng(1210)
+    n, d = 320, 300
+    A = rng.normal(size=(n, d)) + 3.0 * rng.normal(size=(3, d))[rng.integers(0, 3, size=n)]
+    src, dst, w, *_ = oracle.knn_graph(A, 5, None)
+    keys = {(int(a), int(b)): float(c) for a, b, c in zip(src, dst, w)}
+    for j in rng.choice(np.arange(1, n), 290, replace=False):
+        keys.setdefault((0, int(j)), float(rng.uniform(0.05, 0.3)))
+    e = sorted(keys)
+    src = np.array([a for a, _ in e], np.int32)
+    dst = np.array([b for _, b in e], np.int32)
+    w = np.array([keys[k] for k in e])
+    assert np.bincount(np.r_[src, dst], minlength=n).max() > 256
+    _compare_path(A, src, dst, w, [0.05, 0.5], q, "ssnal", 1e-7, tol_oracle=1e-9, x_tol=1e-5)
