@@ -270,23 +270,39 @@ __device__ __forceinline__ void knn_insert_i(int (&bd)[KP], int (&bi)[KP], int d
     }
 }
 
-template <int KP>
+// LDS row stride of a staged candidate tile: dp bytes padded so that the
+// stride in 4-byte banks is 4 modulo 32, so the 16 rows one MFMA operand load
+// touches fall on different banks
+__host__ __device__ constexpr int u8_tile_stride(int dp) {
+    return dp + 4 * ((4 - (dp / 4) % 32 + 32) % 32);
+}
+constexpr int kUDs = kUC + 1;  // distance tile row stride (odd: no bank conflicts)
+
+// Query rows of at most kUAreg x 64 codes keep their MFMA operands in
+// registers for the whole scan; longer rows load them for every tile.
+constexpr int kUAreg = 16;
+
+template <int KP, bool AREG>
 __global__ __launch_bounds__(kBlock) void k_knn_u8(const signed char* __restrict__ Kc,
                                                    const int* __restrict__ nrm, int64_t n, int dp,
                                                    int64_t cols_per_split, double* __restrict__ pd,
                                                    int* __restrict__ pi) {
     extern __shared__ unsigned char smem[];
-    signed char* Bs = reinterpret_cast<signed char*>(smem);         // kUC x dp
-    int* Ds = reinterpret_cast<int*>(smem + size_t(kUC) * dp);      // kUQ x kUC
+    const int bst = u8_tile_stride(dp);
+    signed char* Bs = reinterpret_cast<signed char*>(smem);         // kUC x bst
+    int* Ds = reinterpret_cast<int*>(smem + size_t(kUC) * bst);     // kUQ x kUDs
+    int* Ns = Ds + kUQ * kUDs;                                      // kUC candidate norms
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int64_t q0 = int64_t(blockIdx.x) * kUQ;
     const int64_t c_begin = int64_t(blockIdx.y) * cols_per_split;
     int64_t c_end = c_begin + cols_per_split;
     if (c_end > n) c_end = n;
-    // scan role: row tid / 4 of the block's query rows, quarter tid % 4 of a tile
-    const int srow = tid >> 2, quarter = tid & 3;
+    const int ks = dp / 64;  // MFMA k steps
+    // scan role: query row lane of the block, candidate quarter wave of a tile
+    const int srow = lane, quarter = wave;
     const int64_t qi = q0 + srow;
+    const int nq = qi < n ? nrm[qi] : 0;
     int bd[KP], bi[KP];
 #pragma unroll
     for (int p = 0; p < KP; ++p) {
@@ -296,29 +312,65 @@ __global__ __launch_bounds__(kBlock) void k_knn_u8(const signed char* __restrict
     // MFMA role: 16 query rows per wave; lane -> (row lane % 16, k slot lane / 16)
     const int64_t arow = q0 + wave * 16 + (lane & 15);
     const int kslot = (lane >> 4) * 16;
+    v4i areg[AREG ? kUAreg : 1];
+    if constexpr (AREG) {
+#pragma unroll
+        for (int u = 0; u < kUAreg; ++u) {
+            areg[u] = v4i{0, 0, 0, 0};
+            if (u < ks && arow < n)
+                areg[u] = *reinterpret_cast<const v4i*>(Kc + arow * dp + u * 64 + kslot);
+        }
+    }
     for (int64_t c0 = c_begin; c0 < c_end; c0 += kUC) {
         __syncthreads();
-        // stage the candidate tile (16-byte chunks)
-        const int chunks = kUC * dp / 16;
-        for (int e = tid; e < chunks; e += kBlock) {
-            const int r = (e * 16) / dp, off = (e * 16) % dp;
-            const int64_t row = c0 + r;
-            v4i v = {0, 0, 0, 0};
-            if (row < c_end) v = *reinterpret_cast<const v4i*>(Kc + row * dp + off);
-            *reinterpret_cast<v4i*>(Bs + r * dp + off) = v;
+        // stage the candidate tile (dp / 64 16-byte chunks per thread, loaded
+        // eight at a time before any is stored, so their latencies overlap)
+        // and the candidates' norms
+        for (int b0 = 0; b0 < ks; b0 += 8) {
+            v4i v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                v[u] = v4i{0, 0, 0, 0};
+                const int e = tid + (b0 + u) * kBlock;
+                const int r = (e * 16) / dp, off = (e * 16) % dp;
+                if (b0 + u < ks && c0 + r < c_end)
+                    v[u] = *reinterpret_cast<const v4i*>(Kc + (c0 + r) * dp + off);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = tid + (b0 + u) * kBlock;
+                const int r = (e * 16) / dp, off = (e * 16) % dp;
+                if (b0 + u < ks) *reinterpret_cast<v4i*>(Bs + r * bst + off) = v[u];
+            }
         }
+        if (tid < kUC) Ns[tid] = c0 + tid < c_end ? nrm[c0 + tid] : 0;
         __syncthreads();
         v4i acc[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = v4i{0, 0, 0, 0};
-        for (int kk = 0; kk < dp; kk += 64) {
-            v4i a = {0, 0, 0, 0};
-            if (arow < n) a = *reinterpret_cast<const v4i*>(Kc + arow * dp + kk + kslot);
+        if constexpr (AREG) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const v4i b = *reinterpret_cast<const v4i*>(Bs + (t * 16 + (lane & 15)) * dp + kk +
-                                                            kslot);
-                acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[t], 0, 0, 0);
+            for (int u = 0; u < kUAreg; ++u) {
+                if (u < ks) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const v4i b = *reinterpret_cast<const v4i*>(
+                            Bs + (t * 16 + (lane & 15)) * bst + u * 64 + kslot);
+                        acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(areg[u], b, acc[t], 0, 0,
+                                                                       0);
+                    }
+                }
+            }
+        } else {
+            for (int kk = 0; kk < dp; kk += 64) {
+                v4i a = {0, 0, 0, 0};
+                if (arow < n) a = *reinterpret_cast<const v4i*>(Kc + arow * dp + kk + kslot);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const v4i b = *reinterpret_cast<const v4i*>(
+                        Bs + (t * 16 + (lane & 15)) * bst + kk + kslot);
+                    acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[t], 0, 0, 0);
+                }
             }
         }
         // output element (row 4 (lane / 16) + r, column lane % 16) of each 16 x 16 tile
@@ -328,16 +380,16 @@ __global__ __launch_bounds__(kBlock) void k_knn_u8(const signed char* __restrict
             for (int r = 0; r < 4; ++r) {
                 const int row = wave * 16 + (lane >> 4) * 4 + r;
                 const int col = t * 16 + (lane & 15);
-                Ds[row * kUC + col] = acc[t][r];
+                Ds[row * kUDs + col] = acc[t][r];
             }
         }
         __syncthreads();
         if (qi < n) {
-            const int nq = nrm[qi];
+#pragma unroll 4
             for (int cc = quarter * 16; cc < quarter * 16 + 16; ++cc) {
                 const int64_t j = c0 + cc;
                 if (j >= c_end || j == qi) continue;
-                const int dv = nq + nrm[j] - 2 * Ds[srow * kUC + cc];
+                const int dv = nq + Ns[cc] - 2 * Ds[srow * kUDs + cc];
                 knn_insert_i<KP>(bd, bi, dv, int(j));
             }
         }
@@ -431,7 +483,9 @@ ccm_status knn_graph_u8(const unsigned char* K, int64_t n, int d, double scale, 
                        Kc.as<signed char>(), nrm.as<int>());
     const int64_t qblocks = (n + kUQ - 1) / kUQ;
     const int64_t ctiles = (n + kUC - 1) / kUC;
-    int64_t splits = (1024 + qblocks - 1) / qblocks;
+    // about eight rounds of two blocks per compute unit, so the last round's
+    // tail is a small part of the launch
+    int64_t splits = (4096 + qblocks - 1) / qblocks;
     if (splits > ctiles) splits = ctiles;
     if (splits < 1) splits = 1;
     const int64_t cps = ((ctiles + splits - 1) / splits) * kUC;
@@ -443,14 +497,19 @@ ccm_status knn_graph_u8(const unsigned char* K, int64_t n, int d, double scale, 
     HIPCHK(pi.alloc(size_t(nl) * n * KP * 4, s));
     HIPCHK(nbr.alloc(size_t(cnt) * 4, s));
     HIPCHK(nd2.alloc(size_t(cnt) * 8, s));
-    const size_t lds = size_t(kUC) * dp + size_t(kUQ) * kUC * 4;
+    const size_t lds =
+        size_t(kUC) * u8_tile_stride(dp) + size_t(kUQ) * kUDs * 4 + size_t(kUC) * 4;
     const dim3 grid{unsigned(qblocks), unsigned(splits), 1u};
     auto run = [&](auto KPc) {
         constexpr int kp = decltype(KPc)::value;
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_knn_u8<kp>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        hipLaunchKernelGGL((k_knn_u8<kp>), grid, dim3(kBlock), lds, s, Kc.as<signed char>(),
-                           nrm.as<int>(), n, dp, cps, pd.as<double>(), pi.as<int>());
+        auto go = [&](auto kern) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+            hipLaunchKernelGGL(kern, grid, dim3(kBlock), lds, s, Kc.as<signed char>(),
+                               nrm.as<int>(), n, dp, cps, pd.as<double>(), pi.as<int>());
+        };
+        if (dp <= 64 * kUAreg) go(&k_knn_u8<kp, true>);
+        else go(&k_knn_u8<kp, false>);
         hipLaunchKernelGGL((k_knn_merge<kp>), dim3(flat_grid(n)), dim3(kBlock), 0, s, n, k, nl,
                            pd.as<double>(), pi.as<int>(), nbr.as<int>(), nd2.as<double>());
     };
