@@ -65,9 +65,6 @@ WORKLOADS = {
 
 METRIC = "path wall-time @KKT 1e-6 + edge-op HBM GB/s %peak; plain vs batched/adjoint"
 
-# CG iterations replayed from captured HIP graphs in the legs that run
-# without kernel timing (ccm_options.graphs); set from --graphs
-GRAPHS = 0
 
 
 def log(*a):
@@ -245,7 +242,7 @@ def batched_leg(ccm, torch, count, budget_s):
         dev.append(dict(A=A, src=src, dst=dst, w=w, q=it["q"]))
     torch.cuda.synchronize()
     g = np.logspace(-3, 1, 10)
-    o = ccm.ccm_default_options(time_budget_s=budget_s, graphs=GRAPHS)
+    o = ccm.ccm_default_options(time_budget_s=budget_s)
     t0 = time.perf_counter()
     res = ccm.ccm_solve_path_batched(dev, g, 1e-6, opts=o)
     torch.cuda.synchronize()
@@ -343,7 +340,7 @@ def small_workload_leg(ccm, torch, name, steps=3):
     gammas = np.logspace(lo, hi, int(cnt))
     rec = {"desc": wl["desc"], "n": int(A_np.shape[0]), "d": int(A_np.shape[1])}
     for method, code in (("ssnal", 0), ("admm", 1), ("hpr", 3)):
-        o = ccm.ccm_default_options(method=code, graphs=GRAPHS)
+        o = ccm.ccm_default_options(method=code)
 
         def one():
             t0 = time.perf_counter()
@@ -377,9 +374,6 @@ def main():
                     help="wall-clock budget (s) of each (q, d) group of the batched leg")
     ap.add_argument("--locality", type=int, default=-1, choices=(-1, 0, 1),
                     help="vertex processing order of the library (-1: its default)")
-    ap.add_argument("--graphs", type=int, default=0, choices=(0, 1),
-                    help="replay CG iterations from captured HIP graphs where kernels are "
-                         "not timed")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without HIP events around the matvec launches (roofline then "
                          "omitted)")
@@ -392,8 +386,6 @@ def main():
     import torch
     import paper_2501_15964_amd as ccm
 
-    global GRAPHS
-    GRAPHS = args.graphs
     wl = WORKLOADS[args.workload]
     log(f"generating {args.workload} ...")
     A_np, K_np = make_points(wl)

@@ -106,12 +106,6 @@ typedef struct {
                               the caches hold them); 0: the input order; -1
                               (default): 1 when n d >= 2^22, else 0.  Changes the
                               summation order only, never the data layout */
-    int32_t graphs;        /* 1: CG iterations are replayed two at a time from HIP graphs
-                              captured once per call (same kernels, bit-identical
-                              results, fewer launches); 0 (default): plain launches.
-                              Not used while profile != 0, nor by
-                              ccm_solve_path_batched (whose groups run concurrently
-                              from several host threads) */
     int32_t window_chunk;  /* incidences per row group of a vertex-kernel window; 0
                               (default): the tuned value for the row width and q (a table
                               the package's window tuner writes); changes the summation

@@ -61,8 +61,8 @@ class CcmOptions(ctypes.Structure):
         ("cg_chunk", ctypes.c_int32), ("profile", ctypes.c_int32),
         ("sigma0", ctypes.c_double), ("sigma_max", ctypes.c_double),
         ("tau", ctypes.c_double), ("time_budget_s", ctypes.c_double),
-        ("locality", ctypes.c_int32), ("graphs", ctypes.c_int32),
-        ("window_chunk", ctypes.c_int32), ("dual_scale", ctypes.c_int32),
+        ("locality", ctypes.c_int32), ("window_chunk", ctypes.c_int32),
+        ("dual_scale", ctypes.c_int32),
     ]
 
 

@@ -80,7 +80,6 @@ ccm_options defaults() {
     o.tau = 1.618;
     o.time_budget_s = 0.0;
     o.locality = -1;
-    o.graphs = 0;
     o.dual_scale = -1;
     return o;
 }

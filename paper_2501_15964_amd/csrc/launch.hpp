@@ -227,11 +227,11 @@ struct CgSkip {
     int nparts = 0;
     double thr = 0.0;
     const int* done = nullptr;
-    const double* thr_dev = nullptr;  // if set, the threshold is read here instead of thr
 };
 constexpr int kMatvecNV = 1;
 // SSNAL edge pass fused with the gradient (one launch, vertex-centric; q = 1
-// or 2 only: for q = inf nothing is launched and -1 is returned): Pi =
+// and 2, and q = inf without kpart on rows of 64 lanes; otherwise nothing is
+// launched and -1 is returned): Pi =
 // Pi_C(U + sigma B X) and its Jacobian payload as launch_edge_ssnal, G = X -
 // A + B^T Pi and Dinv as launch_scatter(diag); edge partials (kEdgeSsnalNV)
 // to epart and vertex partials (kScatterNV) to spart, one row per block;
@@ -241,22 +241,17 @@ int launch_edge_grad(const DevGraph& g, int d, int qk, double gamma, double sigm
                      const double* X, const double* U, const double* A, double* Pi, Payload pl,
                      double* G, double* Dinv, double* epart, double* spart, hipStream_t s,
                      double* kpart = nullptr);
-// With sigma_dev set, sigma is read from that device scalar at run time (for
-// launches replayed from a captured graph).
 int launch_matvec(const DevGraph& g, int d, int qk, int mode, const double* V, const double* Pi,
                   Payload pl, double gamma, double sigma, double c0, const double* dscale,
-                  double* out, double* partials, CgSkip skip, hipStream_t s,
-                  const double* sigma_dev = nullptr);
+                  double* out, double* partials, CgSkip skip, hipStream_t s);
 
 // ---- vector kernels (vector_kernels.hip) ----------------------------------
 struct CgBufs {
     double *x, *r, *u, *w, *p, *s;  // n*d each
     double* upd[2];                 // update partials (r.u, r.r) per block, parity buffered
     double* wu[2];                  // matvec partials (w.u) per block, parity buffered
-    double* state;                  // [2][2]: gamma_j, alpha_j per parity; [4] the
-                                    // threshold and [5] sigma of graph-replayed launches
+    double* state;                  // [2][2]: gamma_j, alpha_j per parity
     int* flag;                      // [0] done (1) / breakdown (2), [1] iterations
-    int* jslot;                     // [2]: index j of the next update of each parity
     int nparts;                     // partial count of the update kernel
     int nparts_mv;                  // partial count of the matvec kernel
 };
@@ -266,11 +261,6 @@ void launch_cg_init(int64_t N, const double* b, bool neg, const double* Dinv, Cg
                     hipStream_t s);
 // iteration j of the Chronopoulos-Gear PCG update (see vector_kernels.hip).
 void launch_cg_update(int64_t N, int j, const double* Dinv, CgBufs& cg, double thr, hipStream_t s);
-// The same for a launch replayed from a captured graph: the iteration index
-// comes from cg.jslot[par] and the threshold from cg.state[4] at run time.
-void launch_cg_update_dev(int64_t N, int par, const double* Dinv, CgBufs& cg, hipStream_t s);
-// dst[0] = a, dst[1] = b (stream-ordered, no host memory involved)
-void launch_set2(double* dst, double a, double b, hipStream_t s);
 int cg_update_grid(int64_t N);
 
 // Xt = X + alpha D; partials (2): 1/2 ||Xt - A||^2, <G, D>.

@@ -224,11 +224,6 @@ struct Solver::Impl {
         prof.s = s;
     }
     ~Impl() {
-        for (auto& gk : graphs) {
-            if (gk.exec) (void)hipGraphExecDestroy(gk.exec);
-            if (gk.graph) (void)hipGraphDestroy(gk.graph);
-        }
-        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (hs) (void)hipHostFree(hs);
         if (hflag) (void)hipHostFree(hflag);
         for (auto e : cg_ev)
@@ -306,7 +301,6 @@ struct Solver::Impl {
         cg.wu[1] = pwu1.as<double>();
         cg.state = cgstate.as<double>();
         cg.flag = cgflag.as<int>();
-        cg.jslot = cgflag.as<int>() + 4;
         cg.nparts = cg_update_grid(N);
         return CCM_OK;
     }
@@ -501,57 +495,6 @@ struct Solver::Impl {
         CgPending P[2];
     } cr;
 
-    // ---- CG iterations replayed from captured graphs ---------------------------
-    // A graph holds two iterations (update of odd j, matvec, update of even j,
-    // matvec) whose index, threshold and penalty are read from device memory,
-    // so one capture serves every CG solve with the same buffers.  Graphs are
-    // keyed by the solve's mode and buffers (the Newton systems alternate
-    // between two sets as trial points are accepted).
-    struct CgGraph {
-        int mode;
-        const double *Dv, *Pic;
-        const double2* ipay;
-        const uint32_t* lbits;
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-    };
-    std::vector<CgGraph> graphs;
-    hipStream_t cap_stream = nullptr;
-    // Not in the batched form: its groups run from a pool of host threads,
-    // and a capture on one thread while another allocates work space failed
-    // there with a capture-isolation error.
-    bool use_graphs() const { return o.graphs != 0 && !prof.on && !batch; }
-
-    ccm_status cg_graph(hipGraphExec_t& out) {
-        for (const auto& gk : graphs)
-            if (gk.mode == cr.mode && gk.Dv == cr.Dv && gk.Pic == cr.Pic &&
-                gk.ipay == cr.p.ipay && gk.lbits == cr.p.lbits) {
-                out = gk.exec;
-                return CCM_OK;
-            }
-        if (!cap_stream) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
-        CgGraph gk{cr.mode, cr.Dv, cr.Pic, cr.p.ipay, cr.p.lbits};
-        // relaxed: the capture holds kernel launches only, and no other call
-        // of this or another thread is to be refused while it is open
-        HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed));
-        for (int par = 1; par >= 0; --par) {
-            launch_cg_update_dev(N, par, cr.Dv, cg, cap_stream);
-            CgSkip sk;
-            sk.rr_partials = cg.upd[par ^ 1];
-            sk.nparts = cg.nparts;
-            sk.thr_dev = cg.state + 4;
-            sk.done = cg.flag;
-            launch_matvec(g, d, qk, cr.mode, cg.u, cr.Pic, cr.p, cr.gamma, sigma, 1.0, nullptr,
-                          cg.w, cg.wu[par ^ 1], sk, cap_stream, cg.state + 5);
-        }
-        const hipError_t ce = hipStreamEndCapture(cap_stream, &gk.graph);
-        HIPCHK(ce);
-        HIPCHK(hipGraphInstantiate(&gk.exec, gk.graph, nullptr, nullptr, 0));
-        graphs.push_back(gk);
-        out = gk.exec;
-        return CCM_OK;
-    }
-
     int cg_first(int mode) const {
         const int chunk = std::max(1, o.cg_chunk);
         return std::max(2, std::min(2 * chunk, cg_pred[mode & 1]));
@@ -589,36 +532,6 @@ struct Solver::Impl {
         q.j0 = cr.j;
         q.upd.clear();
         q.mv.clear();
-        if (use_graphs() && count >= 2) {
-            // the threshold and penalty the replayed launches read
-            launch_set2(cg.state + 4, cr.thr, sigma, s);
-            int c = 0;
-            while (c < count && cr.j < o.cg_max_iter) {
-                if ((cr.j & 1) && c + 1 < count && cr.j + 1 < o.cg_max_iter) {
-                    hipGraphExec_t ex = nullptr;
-                    CHK(cg_graph(ex));
-                    HIPCHK(hipGraphLaunch(ex, s));
-                    cr.j += 2;
-                    c += 2;
-                    continue;
-                }
-                launch_cg_update(N, cr.j, cr.Dv, cg, cr.thr, s);
-                CgSkip sk;
-                sk.rr_partials = cg.upd[(cr.j + 1) & 1];
-                sk.nparts = cg.nparts;
-                sk.thr = cr.thr;
-                sk.done = cg.flag;
-                launch_matvec(g, d, qk, cr.mode, cg.u, cr.Pic, cr.p, cr.gamma, sigma, 1.0, nullptr,
-                              cg.w, cg.wu[(cr.j + 1) & 1], sk, s);
-                ++cr.j;
-                ++c;
-            }
-            q.j1 = cr.j;
-            HIPCHK(hipMemcpyAsync(q.hf, cg.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipEventRecord(q.e, s));
-            q.pid_end = prof.next_pair();
-            return CCM_OK;
-        }
         for (int c = 0; c < count && cr.j < o.cg_max_iter; ++c, ++cr.j) {
             const int j = cr.j;
             {

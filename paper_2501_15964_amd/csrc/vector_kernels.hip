@@ -11,8 +11,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t N, const double* __r
                                                     double* __restrict__ x, double* __restrict__ r,
                                                     double* __restrict__ u, double* __restrict__ p,
                                                     double* __restrict__ s,
-                                                    double* __restrict__ upd0, int* flag,
-                                                    int* jslot) {
+                                                    double* __restrict__ upd0, int* flag) {
     double acc[2] = {0.0, 0.0};
     for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < N;
          k += int64_t(gridDim.x) * kBlock) {
@@ -28,7 +27,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t N, const double* __r
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         flag[0] = 0;
         flag[1] = 0;
-        jslot[0] = 0;
     }
 }
 
@@ -41,20 +39,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t N, const double* __r
 // (j = 0: beta = 0, alpha = gamma_0 / delta_0).  Every block re-reduces the
 // partials in the same order, so all blocks agree bit for bit on alpha and
 // beta; scalars and partials alternate between two slots by parity of j.
-// A launch with j < 0 (replayed from a captured graph) takes its index from
-// jslot[par] and its threshold from state[4]; every launch stores the next
-// index in jslot[par ^ 1].
 __global__ __launch_bounds__(kBlock) void k_cg_update(
-    int64_t N, int j, int par, const double* __restrict__ Dinv, double* __restrict__ x,
+    int64_t N, int j, const double* __restrict__ Dinv, double* __restrict__ x,
     double* __restrict__ r, double* __restrict__ u, const double* __restrict__ w,
     double* __restrict__ p, double* __restrict__ s, const double* __restrict__ upd_prev,
     double* __restrict__ upd_next, const double* __restrict__ wu, int nparts_upd, int nparts_mv,
-    double* __restrict__ state, int* flag, int* jslot, double thr) {
+    double* __restrict__ state, int* flag, double thr) {
     if (flag[0]) return;
-    if (j < 0) {
-        j = jslot[par];
-        thr = state[4];
-    }
+    const int par = j & 1;
     // r.r (stop test), gamma = r.u, delta = w.u in one pass
     const double* ptr[3] = {upd_prev + 1, upd_prev, wu};
     const int cnt[3] = {nparts_upd, nparts_upd, nparts_mv};
@@ -125,14 +117,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(
         state[(par ^ 1) * 2 + 0] = gam;
         state[(par ^ 1) * 2 + 1] = alpha;
         flag[1] = j + 1;
-        jslot[par ^ 1] = j + 1;
-    }
-}
-
-__global__ void k_set2(double* dst, double a, double b) {
-    if (threadIdx.x == 0) {
-        dst[0] = a;
-        dst[1] = b;
     }
 }
 
@@ -521,25 +505,15 @@ int cg_update_grid(int64_t N) {
 void launch_cg_init(int64_t N, const double* b, bool neg, const double* Dinv, CgBufs& cg,
                     hipStream_t s) {
     hipLaunchKernelGGL(k_cg_init, dim3(cg_update_grid(N)), dim3(kBlock), 0, s, N, b, neg ? -1.0 : 1.0,
-                       Dinv, cg.x, cg.r, cg.u, cg.p, cg.s, cg.upd[0], cg.flag, cg.jslot);
+                       Dinv, cg.x, cg.r, cg.u, cg.p, cg.s, cg.upd[0], cg.flag);
 }
 
 void launch_cg_update(int64_t N, int j, const double* Dinv, CgBufs& cg, double thr,
                       hipStream_t s) {
     const int par = j & 1;
-    hipLaunchKernelGGL(k_cg_update, dim3(cg_update_grid(N)), dim3(kBlock), 0, s, N, j, par, Dinv,
+    hipLaunchKernelGGL(k_cg_update, dim3(cg_update_grid(N)), dim3(kBlock), 0, s, N, j, Dinv,
                        cg.x, cg.r, cg.u, cg.w, cg.p, cg.s, cg.upd[par], cg.upd[par ^ 1],
-                       cg.wu[par], cg.nparts, cg.nparts_mv, cg.state, cg.flag, cg.jslot, thr);
-}
-
-void launch_cg_update_dev(int64_t N, int par, const double* Dinv, CgBufs& cg, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update, dim3(cg_update_grid(N)), dim3(kBlock), 0, s, N, -1, par, Dinv,
-                       cg.x, cg.r, cg.u, cg.w, cg.p, cg.s, cg.upd[par], cg.upd[par ^ 1],
-                       cg.wu[par], cg.nparts, cg.nparts_mv, cg.state, cg.flag, cg.jslot, 0.0);
-}
-
-void launch_set2(double* dst, double a, double b, hipStream_t s) {
-    hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, s, dst, a, b);
+                       cg.wu[par], cg.nparts, cg.nparts_mv, cg.state, cg.flag, thr);
 }
 
 int launch_trial(int64_t N, const double* X, const double* D, double alpha, const double* A,

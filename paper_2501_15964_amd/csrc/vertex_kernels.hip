@@ -720,7 +720,6 @@ struct MatvecOut {
     double sigma, c0;
     const double* dscale;
     double* out;
-    const double* sigma_dev;  // if set, sigma is read here at run time
 };
 
 template <int LPR, int NPER>
@@ -743,9 +742,8 @@ __device__ __forceinline__ void matvec_finish(int64_t v, int d, int gl, const Ma
 __device__ __forceinline__ bool cg_skip(const CgSkip& skip) {
     const int dn = skip.done ? *skip.done : 0;
     if (skip.rr_partials) {
-        const double thr = skip.thr_dev ? *skip.thr_dev : skip.thr;
         const double rr = block_sum_partials(skip.rr_partials, skip.nparts, 2, 1);
-        if (rr <= thr) return true;
+        if (rr <= skip.thr) return true;
     }
     return dn != 0;
 }
@@ -817,7 +815,6 @@ __global__ __launch_bounds__(kBlock, matvec_min_waves<NPER>()) void k_matvec_win
                                                        double* __restrict__ partials,
                                                        CgSkip skip) {
     if (cg_skip(skip)) return;
-    if (mo.sigma_dev) mo.sigma = *mo.sigma_dev;
     constexpr int U = Unroll<NPER>::U;
     constexpr bool PAY = MODE != 1;
     constexpr int QP = MODE == 2 ? kQ2 : Q;
@@ -1036,11 +1033,10 @@ int launch_edge_grad(const DevGraph& g, int d, int qk, double gamma, double sigm
 
 int launch_matvec(const DevGraph& g, int d, int qk, int mode, const double* V, const double* Pi,
                   Payload pl, double gamma, double sigma, double c0, const double* dscale,
-                  double* out, double* partials, CgSkip skip, hipStream_t s,
-                  const double* sigma_dev) {
+                  double* out, double* partials, CgSkip skip, hipStream_t s) {
     (void)gamma;  // the Jacobian payload already holds 1 / (gamma w)
     int total = 0;
-    MatvecOut mo{sigma, c0, dscale, out, sigma_dev};
+    MatvecOut mo{sigma, c0, dscale, out};
     dispatch_row(d, [&](auto L, auto N) {
         constexpr int lpr = decltype(L)::value, nper = decltype(N)::value;
         const int g1 = window_grid<lpr>(g);

@@ -29,7 +29,7 @@ def test_struct_sizes():
     assert ctypes.sizeof(ccm.CcmStats) == 144
     o = ccm.ccm_default_options()
     assert o.method == 0 and o.max_outer == 300 and o.cg_max_iter == 500
-    assert o.locality == -1 and o.time_budget_s == 0.0 and o.graphs == 0 and o.window_chunk == 0
+    assert o.locality == -1 and o.time_budget_s == 0.0 and o.window_chunk == 0
     assert o.dual_scale == -1
     assert ccm.ccm_version().startswith("libccm")
 
