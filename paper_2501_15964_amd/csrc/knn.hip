@@ -283,7 +283,7 @@ constexpr int kUDs = kUC + 1;  // distance tile row stride (odd: no bank conflic
 constexpr int kUAreg = 16;
 
 template <int KP, bool AREG>
-__global__ __launch_bounds__(kBlock) void k_knn_u8(const signed char* __restrict__ Kc,
+__global__ __launch_bounds__(kBlock, 2) void k_knn_u8(const signed char* __restrict__ Kc,
                                                    const int* __restrict__ nrm, int64_t n, int dp,
                                                    int64_t cols_per_split, double* __restrict__ pd,
                                                    int* __restrict__ pi) {
@@ -321,30 +321,44 @@ __global__ __launch_bounds__(kBlock) void k_knn_u8(const signed char* __restrict
                 areg[u] = *reinterpret_cast<const v4i*>(Kc + arow * dp + u * 64 + kslot);
         }
     }
+    // A tile is staged as dp / 64 16-byte chunks per thread, loaded eight at
+    // a time before any is stored, so their latencies overlap; the first
+    // four chunks of the next tile are loaded while this tile is multiplied
+    // and scanned.
+    constexpr int kPre = 4;
+    auto load = [&](int64_t c, int b0, int cnt, v4i* v) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (u >= cnt) break;
+            v[u] = v4i{0, 0, 0, 0};
+            const int e = tid + (b0 + u) * kBlock;
+            const int r = (e * 16) / dp, off = (e * 16) % dp;
+            if (b0 + u < ks && c + r < c_end)
+                v[u] = *reinterpret_cast<const v4i*>(Kc + (c + r) * dp + off);
+        }
+    };
+    auto store = [&](int b0, int cnt, const v4i* v) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (u >= cnt) break;
+            const int e = tid + (b0 + u) * kBlock;
+            const int r = (e * 16) / dp, off = (e * 16) % dp;
+            if (b0 + u < ks) *reinterpret_cast<v4i*>(Bs + r * bst + off) = v[u];
+        }
+    };
+    v4i pre[kPre];
+    if (c_begin < c_end) load(c_begin, 0, kPre, pre);
     for (int64_t c0 = c_begin; c0 < c_end; c0 += kUC) {
         __syncthreads();
-        // stage the candidate tile (dp / 64 16-byte chunks per thread, loaded
-        // eight at a time before any is stored, so their latencies overlap)
-        // and the candidates' norms
-        for (int b0 = 0; b0 < ks; b0 += 8) {
+        store(0, kPre, pre);
+        for (int b0 = kPre; b0 < ks; b0 += 8) {
             v4i v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                v[u] = v4i{0, 0, 0, 0};
-                const int e = tid + (b0 + u) * kBlock;
-                const int r = (e * 16) / dp, off = (e * 16) % dp;
-                if (b0 + u < ks && c0 + r < c_end)
-                    v[u] = *reinterpret_cast<const v4i*>(Kc + (c0 + r) * dp + off);
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = tid + (b0 + u) * kBlock;
-                const int r = (e * 16) / dp, off = (e * 16) % dp;
-                if (b0 + u < ks) *reinterpret_cast<v4i*>(Bs + r * bst + off) = v[u];
-            }
+            load(c0, b0, 8, v);
+            store(b0, 8, v);
         }
         if (tid < kUC) Ns[tid] = c0 + tid < c_end ? nrm[c0 + tid] : 0;
         __syncthreads();
+        if (c0 + kUC < c_end) load(c0 + kUC, 0, kPre, pre);
         v4i acc[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = v4i{0, 0, 0, 0};
