@@ -106,11 +106,11 @@ typedef struct {
                               the caches hold them); 0: the input order; -1
                               (default): 1 when n d >= 2^22, else 0.  Changes the
                               summation order only, never the data layout */
-    int32_t window_chunk;  /* incidences per row group of a vertex-kernel window; 0
-                              (default): the tuned value for the row width and q (a table
-                              the package's window tuner writes); changes the summation
-                              order of split vertices, so results depend on it (each value
-                              deterministic) */
+    int32_t window_chunk;  /* incidences per row group of a vertex-kernel window, 1 to
+                              4096 (else CCM_E_INVALID); 0 (default): the tuned value for
+                              the row width and q (a table the package's window tuner
+                              writes); changes the summation order of split vertices, so
+                              results depend on it (each value deterministic) */
     int32_t dual_scale;    /* SSNAL path continuation.  1: before each gamma after the
                               first, the rows of U on the boundary of the previous gamma's
                               dual balls (q = 1: the coordinates at +-r) are scaled by
@@ -118,7 +118,8 @@ typedef struct {
                               apart is gamma w_l times a direction that moves slowly along
                               the path.  0: (X, U) carried over unchanged.  -1 (default):
                               1 for q = 2, 0 otherwise (measured faster, resp. slower).
-                              Only the starting point changes, not the solution */
+                              Other values: CCM_E_INVALID.  Only the starting point
+                              changes, not the solution */
 } ccm_options;
 
 ccm_options ccm_default_options(void);
