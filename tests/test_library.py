@@ -40,3 +40,27 @@ def test_binding_wraps_every_compute_entry_point():
     for name in pkg.EXPORTED_SYMBOLS:
         if name not in helpers:
             assert name in pkg.__all__ and callable(getattr(pkg, name)), name
+
+
+def _header_struct_fields(name):
+    text = open(os.path.join(ROOT, "include", "ccm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    end = re.search(r"\}\s*" + name + r"\s*;", text).start()
+    body = text[text.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, names = decl.split(None, 1)
+        for nm in names.split(","):
+            fields.append(re.sub(r"\[.*\]", "", nm).strip())
+    return fields
+
+
+def test_binding_structs_follow_the_header():
+    # the ctypes layouts name the header's fields in the header's order, so a
+    # field added to one side only fails here instead of shifting the others
+    for cname, pyclass in (("ccm_options", ccm.CcmOptions), ("ccm_stats", ccm.CcmStats),
+                           ("ccm_instance", ccm.CcmInstance)):
+        assert [f[0] for f in pyclass._fields_] == _header_struct_fields(cname), cname
